@@ -1,0 +1,166 @@
+"""Seeded synthetic inputs for the DF-DSRG-PT2 virtual-density pass.
+
+This module is shared by the FP64 oracle, the tests and the benchmark.  It draws
+random numbers and lays them out; it holds none of the method's arithmetic (no
+integrals, amplitudes, energies or densities are formed here).
+
+Inputs of the pass (paper Sec. 2 and App. A):
+  * semicanonical orbital energies of the correlated core holes, of the active
+    holes and of the virtuals (the diagonal Fock blocks of Eq. A5),
+  * the spin-summed active one-body density Gamma_act (Eq. A1), symmetric,
+    eigenvalues in [0, 2],
+  * density-fitted three-index integrals B^Q_ia for holes i and virtuals a
+    (the paper uses DF integrals with one common auxiliary basis, Sec. 3).
+
+The molecules of the paper are not available, so every input is drawn from the
+distributions below, shaped like the paper's workloads (Sec. 3: Ni(CO)4 with
+N_V = 539 virtuals; FeCl(Cor) with more than 1000 basis functions).
+
+Recipe (random stream ``numpy.random.default_rng(seed)``, PCG64), draws in
+this order:
+  1. core (or closed-shell occupied) energies  U[-1.5, -0.3] Eh, sorted ascending
+  2. virtual energies                          U[ 0.1,  5.0] Eh, sorted ascending
+  3. (active space only) active energies       U[-0.3,  0.0] Eh, sorted ascending
+     then x ~ U[0, 2]^(n_act/2) and a standard-normal n_act x n_act matrix G;
+     Gamma_act = Q diag(x, 2 - x) Q^T with Q from the QR factorization of G,
+     columns signed so that R has a positive diagonal (Haar-distributed Q);
+     trace(Gamma_act) = n_act exactly.
+  4. Z ~ N(0, 1) with C-order shape (n_aux, n_h, n_v)
+  5. (low-rank variant only) P ~ N(0,1)^(n_aux x 64), R ~ N(0,1)^(64 x n_h*n_v)
+  6. (localized variant only) hole positions x_i ~ U[0, 40], aux positions
+     y_Q ~ U[0, 40]
+  B^Q_ia = d_a * (Z^Q_ia [+ (P R)^Q_ia / 8]) [* exp(-|x_i - y_Q| / xi)],
+  with the virtual decay d_a = 0.3 / (1 + eps_a) * 0.2.
+
+Holes are ordered core first, then active.  B is returned in the layout the
+library consumes, ``B[i, a, Q]`` (hole, virtual, auxiliary; auxiliary fastest),
+FP64, C-contiguous.  It is filled chunk by chunk over Q from the same random
+stream, so the values do not depend on the chunk size.
+"""
+from __future__ import annotations
+
+import dataclasses
+from typing import Optional
+
+import numpy as np
+
+__all__ = ["Inputs", "generate", "CONFIGS", "config_inputs", "input_recipe"]
+
+
+@dataclasses.dataclass
+class Inputs:
+    eps_core: np.ndarray          # [n_core]
+    eps_act: np.ndarray           # [n_act]
+    eps_vir: np.ndarray           # [n_vir], ascending
+    gamma_act: np.ndarray         # [n_act, n_act], symmetric (empty if n_act == 0)
+    B: np.ndarray                 # [n_h, n_vir, n_aux]
+    seed: int = 0
+    label: str = ""
+
+    @property
+    def n_core(self) -> int:
+        return int(self.eps_core.shape[0])
+
+    @property
+    def n_act(self) -> int:
+        return int(self.eps_act.shape[0])
+
+    @property
+    def n_h(self) -> int:
+        return self.n_core + self.n_act
+
+    @property
+    def n_vir(self) -> int:
+        return int(self.eps_vir.shape[0])
+
+    @property
+    def n_aux(self) -> int:
+        return int(self.B.shape[2])
+
+    @property
+    def eps_hole(self) -> np.ndarray:
+        return np.concatenate([self.eps_core, self.eps_act])
+
+    def replace(self, **kw) -> "Inputs":
+        return dataclasses.replace(self, **kw)
+
+
+def _haar_orthogonal(rng: np.random.Generator, n: int) -> np.ndarray:
+    g = rng.standard_normal((n, n))
+    q, r = np.linalg.qr(g)
+    return q * np.sign(np.diag(r))[None, :]
+
+
+def generate(n_core: int, n_act: int, n_vir: int, n_aux: int, seed: int = 0, *,
+             low_rank: int = 0, localized_xi: Optional[float] = None,
+             q_chunk: int = 256, label: str = "") -> Inputs:
+    """Draw one input set following the recipe in the module docstring."""
+    if n_act % 2:
+        raise ValueError("n_act must be even (eigenvalues come in pairs x, 2-x)")
+    rng = np.random.default_rng(seed)
+    eps_core = np.sort(rng.uniform(-1.5, -0.3, n_core))
+    eps_vir = np.sort(rng.uniform(0.1, 5.0, n_vir))
+    if n_act:
+        eps_act = np.sort(rng.uniform(-0.3, 0.0, n_act))
+        x = rng.uniform(0.0, 2.0, n_act // 2)
+        q = _haar_orthogonal(rng, n_act)
+        lam = np.concatenate([x, 2.0 - x])
+        gamma = (q * lam[None, :]) @ q.T
+        gamma = 0.5 * (gamma + gamma.T)
+    else:
+        eps_act = np.zeros(0)
+        gamma = np.zeros((0, 0))
+    n_h = n_core + n_act
+    d = 0.3 / (1.0 + eps_vir) * 0.2                     # virtual decay d_a
+    B = np.empty((n_h, n_vir, n_aux), dtype=np.float64)
+    for q0 in range(0, n_aux, q_chunk):
+        q1 = min(n_aux, q0 + q_chunk)
+        z = rng.standard_normal((q1 - q0, n_h, n_vir))
+        B[:, :, q0:q1] = z.transpose(1, 2, 0)
+    if low_rank:
+        p = rng.standard_normal((n_aux, low_rank))
+        r = rng.standard_normal((low_rank, n_h * n_vir))
+        scale = 1.0 / np.sqrt(low_rank)
+        for q0 in range(0, n_aux, q_chunk):
+            q1 = min(n_aux, q0 + q_chunk)
+            add = (p[q0:q1] @ r).reshape(q1 - q0, n_h, n_vir) * scale
+            B[:, :, q0:q1] += add.transpose(1, 2, 0)
+    B *= d[None, :, None]
+    if localized_xi is not None:
+        xh = rng.uniform(0.0, 40.0, n_h)
+        yq = rng.uniform(0.0, 40.0, n_aux)
+        B *= np.exp(-np.abs(xh[:, None] - yq[None, :]) / localized_xi)[:, None, :]
+    return Inputs(eps_core=eps_core, eps_act=eps_act, eps_vir=eps_vir,
+                  gamma_act=gamma, B=B, seed=seed, label=label)
+
+
+# Workload presets.  Sizes are (n_core, n_act, n_vir, n_aux).
+CONFIGS = {
+    # closed shell, small enough for the oracle in well under a second
+    "c1": dict(sizes=(10, 0, 60, 200), s=(0.5,), p_o=(0.985,), precision="fp64",
+               gen=dict()),
+    # active space (trace-8 Gamma_act) and a rank-64 shared component in B
+    "c2": dict(sizes=(40, 8, 400, 1600), s=(0.5,), p_o=(0.98, 0.985, 0.99),
+               precision="fp64", gen=dict(low_rank=64)),
+    # ~1300 basis functions, closed shell, split-BF16 GEMMs
+    "c3": dict(sizes=(80, 0, 1200, 4000), s=(0.5, 1.0), p_o=(0.985,),
+               precision="bf16", gen=dict()),
+    # learned pair screening: train at c1 sizes over seeds 1..200, apply at c3 sizes
+    "c4": dict(sizes=(80, 0, 1200, 4000), s=(0.5,), p_o=(0.985,), precision="bf16",
+               gen=dict(), train_sizes=(10, 0, 60, 200), train_seeds=(1, 200)),
+    # largest one-GPU instance, trace-12 Gamma_act
+    "c5": dict(sizes=(120, 12, 2000, 6000), s=(0.5,), p_o=(0.985,), precision="fp8",
+               gen=dict()),
+}
+
+
+def config_inputs(name: str, seed: int = 0, **over) -> Inputs:
+    cfg = CONFIGS[name]
+    n_core, n_act, n_vir, n_aux = cfg["sizes"]
+    kw = dict(cfg["gen"])
+    kw.update(over)
+    return generate(n_core, n_act, n_vir, n_aux, seed, label=name, **kw)
+
+
+def input_recipe() -> str:
+    return __doc__
