@@ -1,0 +1,170 @@
+/*
+ * dfpt2.h -- C ABI of libdfpt2.so, the MI355X (gfx950) DF-DSRG-PT2 virtual
+ * natural-orbital pass of frozen-natural-orbital SA-DSRG
+ * (Li, Mao, Huang, Evangelista, arXiv 2312.07008).
+ *
+ * What the library computes (paper Sec. 2 and App. A):
+ *   For every ordered hole pair (i, j) and virtuals a, b:
+ *     V^{ij}_{ab} = sum_Q B^Q_ia B^Q_jb                    density-fitted <ab|ij> (Sec. 3)
+ *     Delta       = eps_i + eps_j - eps_a - eps_b          (after Eq. A7)
+ *     t^{ij}_{ab} = V (1 - exp(-s Delta^2)) / Delta         (Eq. A7)
+ *     Vr^{ij}_{ab}= V (1 + exp(-s Delta^2))                 renormalized integrals
+ *   the PT2 energy  E  = 1/4 sum_{ijkl} gamma_ik gamma_jl <Vr_ij, 2T_kl - T_kl^T>,
+ *   and the virtual block of the unrelaxed second-order 1-RDM (Eq. A9 with zero
+ *   cumulants and no singles)
+ *                   D  = 1/2 sum_{ijkl} gamma_ik gamma_jl T_ij (2T_kl - T_kl^T)^T,
+ *   gamma = 2 I_core (+) Gamma_act the spin-summed hole density (Eq. A1).
+ *   fno_truncate diagonalizes D (Eq. 8) and keeps the natural orbitals whose
+ *   cumulative occupation reaches p_o (Eq. 10), optionally widened over
+ *   near-degenerate occupations (Sec. 2, after Eq. 10).
+ *   pt2_energy_correction recanonicalizes the kept space (Sec. 2), recomputes E
+ *   there and returns E(full) - E(kept), the scalar part of Eq. 11.
+ *
+ * Conventions shared by every entry point:
+ *   * Arrays are row-major.  Every array argument is a DEVICE pointer owned by
+ *     the caller unless the comment says "host".  The library never keeps a
+ *     pointer after the call returns and allocates no device memory: scratch
+ *     space is the caller's `workspace` of `ws_bytes` bytes (query the size
+ *     first).  All device work is enqueued on `stream` (a hipStream_t; NULL is
+ *     the default stream).  Entry points that return a host scalar synchronize
+ *     that stream before returning.
+ *   * Arguments are validated on the host before anything is launched; a bad
+ *     argument returns DFPT2_ERR_INVALID_ARG and leaves every output untouched.
+ *   * Errors are reported only through the return status; nothing throws
+ *     across the ABI.  dfpt2_last_error() gives a message for the calling
+ *     thread's last failure.
+ *   * Holes are ordered core first, then active.  Virtual energies must be
+ *     ascending.  B is laid out [n_h][n_vir][n_aux] (auxiliary index fastest).
+ */
+#ifndef DFPT2_H
+#define DFPT2_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef void* dfpt2_stream_t; /* a hipStream_t */
+
+typedef enum {
+  DFPT2_OK = 0,
+  DFPT2_ERR_INVALID_ARG = -1,   /* null pointer, bad size, s <= 0, p_o outside (0,1], ... */
+  DFPT2_ERR_WORKSPACE = -2,     /* ws_bytes smaller than the queried size */
+  DFPT2_ERR_HIP = -3,           /* a HIP runtime call or kernel launch failed */
+  DFPT2_ERR_NOT_CONVERGED = -4, /* the eigensolver hit its iteration cap */
+  DFPT2_ERR_NONFINITE = -5,     /* a non-finite energy or occupation was produced */
+  DFPT2_ERR_UNSUPPORTED = -6    /* option combination not implemented */
+} dfpt2_status;
+
+typedef enum {
+  DFPT2_FP64 = 0,         /* FP64 MFMA for both contractions */
+  DFPT2_BF16_SLICED = 1,  /* B and T split into BF16 slices; exact FP32 chunk sums, FP64 across chunks */
+  DFPT2_FP8_SLICED = 2    /* FP8 e4m3 slices with per-block power-of-two scales */
+} dfpt2_precision;
+
+typedef struct dfpt2_opts {
+  int64_t n_core;   /* correlated core holes (doubly occupied) */
+  int64_t n_act;    /* active holes; their density is gamma_act */
+  int64_t n_vir;    /* virtual orbitals */
+  int64_t n_aux;    /* auxiliary (density-fitting) functions */
+  double  s;        /* DSRG flow parameter s (Eh^-2), > 0 */
+  int32_t precision;          /* dfpt2_precision */
+  int32_t slices_gemm1;       /* slices per operand of V = B B^T; 0 = precision default */
+  int32_t slices_gemm2;       /* slices per operand of the density product; 0 = default */
+  int32_t density_convention; /* 0: spin-summed Gamma^(2)_vv (Eq. A9); 1: per spin (half) */
+  int64_t pair_batch;         /* unordered pairs per batch; 0 = library default */
+} dfpt2_opts;
+
+/* Message for the calling thread's last failing call ("" if none).  Host string,
+ * owned by the library, valid until the next call on the same thread. */
+const char* dfpt2_last_error(void);
+const char* dfpt2_status_string(int status);
+/* Library version string (host, static). */
+const char* dfpt2_version(void);
+
+/* Workspace (bytes) needed by dfpt2_build_vv_density for these options.
+ * bytes: host out. */
+int dfpt2_workspace_size(const dfpt2_opts* opts, size_t* bytes);
+
+/*
+ * The DF-DSRG-PT2 pass: energy and virtual 1-RDM (App. A Eqs. A7, A9; Eq. 7).
+ *   opts        host pointer to the options
+ *   eps_hole    [n_h]            semicanonical hole energies (core, then active)
+ *   eps_vir     [n_vir]          semicanonical virtual energies, ascending
+ *   gamma_act   [n_act*n_act]    spin-summed active 1-RDM, symmetric; NULL iff n_act == 0
+ *   B           [n_h][n_vir][n_aux] FP64 three-index integrals
+ *   pair_mask   [n_h*n_h] uint8, symmetric, 1 = compute the pair; NULL = all pairs.
+ *               A masked pair contributes nothing to E and D.  Masks are honoured
+ *               for core-core pairs; pairs with an active hole are always computed.
+ *   D_vv        [n_vir*n_vir] out, symmetric
+ *   e_pt2       [2] out, the energy as a double-double (hi, lo)
+ *   pair_energy [n_h*n_h] out or NULL: <Vr_ij, 2T_ij - T_ij^T> of each core-core
+ *               ordered pair (symmetric); 0 for masked pairs, NaN for pairs with an
+ *               active hole
+ *   pair_tnorm  [n_h*n_h] out or NULL: ||T_ij||_F (float), symmetric
+ *   workspace   device scratch of ws_bytes bytes (see dfpt2_workspace_size)
+ * Errors: INVALID_ARG, WORKSPACE, HIP, NONFINITE (energy not finite), UNSUPPORTED.
+ */
+int dfpt2_build_vv_density(const dfpt2_opts* opts,
+                           const double* eps_hole, const double* eps_vir,
+                           const double* gamma_act, const double* B,
+                           const uint8_t* pair_mask,
+                           double* D_vv, double* e_pt2,
+                           double* pair_energy, float* pair_tnorm,
+                           void* workspace, size_t ws_bytes, dfpt2_stream_t stream);
+
+/* Workspace (bytes) for fno_truncate / dfpt2_eigh_sym at dimension n.  bytes: host out. */
+int fno_truncate_workspace_size(int64_t n_vir, size_t* bytes);
+
+/*
+ * Natural orbitals and truncation (Eqs. 8 and 10; near-degeneracy rule of Sec. 2).
+ *   D_vv          [n_vir*n_vir] symmetric input (not modified)
+ *   p_o           cumulative-occupation threshold in (0, 1]
+ *   degen_rel_tol 0 disables the near-degeneracy widening; > 0 keeps adding NOs p
+ *                 beyond the cut while n_last - n_p < degen_rel_tol * n_last, with
+ *                 n_last the smallest occupation the threshold kept (anchored reading)
+ *   occ           [n_vir] out, occupation numbers in descending order
+ *   no_vecs       [n_vir*n_vir] out, column k is the NO of occ[k], oriented so that
+ *                 its largest-magnitude component is positive
+ *   n_kept        host out, N'
+ *   margins       host out [2] or NULL: (p_o - c(N'-1), c(N') - p_o), c = cumulative
+ *                 occupation fraction
+ * Errors: INVALID_ARG, WORKSPACE, HIP, NOT_CONVERGED, NONFINITE.
+ */
+int fno_truncate(const double* D_vv, int64_t n_vir, double p_o, double degen_rel_tol,
+                 double* occ, double* no_vecs, int64_t* n_kept, double* margins,
+                 void* workspace, size_t ws_bytes, dfpt2_stream_t stream);
+
+/* Symmetric FP64 eigensolver used by fno_truncate (Eq. 8) and the
+ * recanonicalization: A [n*n] symmetric (not modified); w [n] out ascending;
+ * Z [n*n] out, column k is the eigenvector of w[k]. */
+int dfpt2_eigh_sym(const double* A, int64_t n, double* w, double* Z,
+                   void* workspace, size_t ws_bytes, dfpt2_stream_t stream);
+
+/* Workspace (bytes) for pt2_energy_correction.  bytes: host out. */
+int pt2_correction_workspace_size(const dfpt2_opts* opts, int64_t n_kept, size_t* bytes);
+
+/*
+ * Additive PT2 correction (Eq. 11, scalar part) for a truncated virtual space.
+ *   opts, eps_hole, eps_vir, gamma_act, B   as for dfpt2_build_vv_density
+ *   no_vecs     [n_vir*n_vir] NOs (columns, descending occupation) from fno_truncate
+ *   n_kept      N', 1 <= N' <= n_vir; the first N' columns span the kept space
+ *   e_full      [2] the full-space energy (double-double) from dfpt2_build_vv_density
+ *   e_kept      [2] out, E_PT2 in the recanonicalized kept basis
+ *   correction  [2] out, e_full - e_kept
+ * The kept space is recanonicalized: F' = V_k^T diag(eps_vir) V_k = W diag(eps~) W^T,
+ * U = V_k W, B~_i = U^T B_i, and the pass is repeated with (eps~, B~).
+ * Errors: INVALID_ARG, WORKSPACE, HIP, NOT_CONVERGED, NONFINITE, UNSUPPORTED.
+ */
+int pt2_energy_correction(const dfpt2_opts* opts, const double* eps_hole, const double* eps_vir,
+                          const double* gamma_act, const double* B, const double* no_vecs,
+                          int64_t n_kept, const double* e_full, double* e_kept,
+                          double* correction, void* workspace, size_t ws_bytes,
+                          dfpt2_stream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DFPT2_H */

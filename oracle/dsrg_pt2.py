@@ -112,7 +112,7 @@ class PassResult:
 
 def pt2_pass(eps_core: np.ndarray, eps_act: np.ndarray, eps_vir: np.ndarray,
              gamma_act: np.ndarray, B: np.ndarray, s: float,
-             with_density: bool = True) -> PassResult:
+             with_density: bool = True, pair_mask: Optional[np.ndarray] = None) -> PassResult:
     """Energy and Gamma^(2)_vv of DF-DSRG-PT2 (Eq. 7, App. A Eqs. A7 and A9).
 
     Gamma^(2)_ef =  2 t^{mn}_{ee'} tc^{mn}_{fe'}                       (core-core)
@@ -120,6 +120,9 @@ def pt2_pass(eps_core: np.ndarray, eps_act: np.ndarray, eps_vir: np.ndarray,
                  +  t^{uv}_{ee'} t^{xy}_{fe'} Gamma^{uv}_{xy}           (active-active)
     with S(A^{pq} B^{rs}) = A^{pq} B^{rs} + A^{qp} B^{sr} and, for zero cumulant,
     Gamma^{uv}_{xy} = Gamma^u_x Gamma^v_y - 1/2 Gamma^v_x Gamma^u_y.
+
+    ``pair_mask`` (n_h x n_h, symmetric) drops core-core pairs whose entry is 0
+    from both sums; pairs with an active hole are always kept.
     """
     n_core, n_act, n_v = eps_core.shape[0], eps_act.shape[0], eps_vir.shape[0]
     n_h = n_core + n_act
@@ -142,6 +145,9 @@ def pt2_pass(eps_core: np.ndarray, eps_act: np.ndarray, eps_vir: np.ndarray,
     # core-core term: 2 t^{mn}_{ee'} tc^{mn}_{fe'}; energy weight 1/4 * 2 * 2
     for m in core:
         for n in core:
+            if pair_mask is not None and not pair_mask[m, n]:
+                pair_energy[m, n] = 0.0
+                continue
             T, Vr = amps(m, n)
             Tc = tcheck(T)
             e = float(np.sum(Vr * Tc))
@@ -200,9 +206,9 @@ def pt2_pass(eps_core: np.ndarray, eps_act: np.ndarray, eps_vir: np.ndarray,
                       pair_energy=pair_energy, pair_tnorm=pair_tnorm)
 
 
-def pt2_pass_inputs(inp, s: float, with_density: bool = True) -> PassResult:
+def pt2_pass_inputs(inp, s: float, with_density: bool = True, pair_mask=None) -> PassResult:
     return pt2_pass(inp.eps_core, inp.eps_act, inp.eps_vir, inp.gamma_act, inp.B, s,
-                    with_density=with_density)
+                    with_density=with_density, pair_mask=pair_mask)
 
 
 def pair_values(inp, i: int, j: int, s: float) -> Tuple[float, float]:

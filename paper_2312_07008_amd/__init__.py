@@ -1,0 +1,10 @@
+"""MI355X-native DF-DSRG-PT2 virtual natural-orbital pass (arXiv 2312.07008).
+
+The computation lives in libdfpt2.so (hand-written HIP for gfx950, C ABI in
+include/dfpt2.h).  This package only loads it and marshals torch device
+tensors into its entry points; there is no CPU fallback.
+"""
+from ._lib import (BF16_SLICED, FP8_SLICED, FP64, DfptError, Opts, LIB_PATH, load)  # noqa: F401
+from .api import (build_vv_density, eigh_sym, fno_truncate, fno_truncate_workspace_size,  # noqa: F401
+                  make_opts, pt2_correction_workspace_size, pt2_energy_correction, upload_inputs,
+                  workspace_size)

@@ -1,0 +1,186 @@
+"""Python binding of libdfpt2.so: argument marshalling only.
+
+Every entry point mirrors the C function of the same name in include/dfpt2.h.
+Tensors must already live on the GPU; torch provides device memory and the
+current stream and nothing else.  Outputs not passed in are allocated with
+torch.empty on the device of the inputs.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional
+
+import torch
+
+from . import _lib
+from ._lib import Opts, check
+
+__all__ = ["make_opts", "workspace_size", "build_vv_density", "fno_truncate_workspace_size",
+           "fno_truncate", "eigh_sym", "pt2_correction_workspace_size", "pt2_energy_correction",
+           "upload_inputs"]
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _need(t: torch.Tensor, name: str, dtype, numel: int):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must be a GPU tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must have dtype {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if t.numel() != numel:
+        raise ValueError(f"{name} must have {numel} elements, got {t.numel()}")
+
+
+def make_opts(n_core: int, n_act: int, n_vir: int, n_aux: int, s: float, precision: int = _lib.FP64,
+              slices_gemm1: int = 0, slices_gemm2: int = 0, density_convention: int = 0,
+              pair_batch: int = 0) -> Opts:
+    return Opts(n_core, n_act, n_vir, n_aux, float(s), precision, slices_gemm1, slices_gemm2,
+                density_convention, pair_batch)
+
+
+def workspace_size(opts: Opts) -> int:
+    lib = _lib.load()
+    n = ctypes.c_size_t(0)
+    check(lib.dfpt2_workspace_size(ctypes.byref(opts), ctypes.byref(n)))
+    return int(n.value)
+
+
+def _workspace(nbytes: int, device, workspace: Optional[torch.Tensor]):
+    if workspace is not None:
+        if workspace.device.type != "cuda" or workspace.dtype != torch.uint8:
+            raise TypeError("workspace must be a uint8 GPU tensor")
+        return workspace
+    return torch.empty(max(nbytes, 1), dtype=torch.uint8, device=device)
+
+
+def build_vv_density(opts: Opts, eps_hole: torch.Tensor, eps_vir: torch.Tensor,
+                     gamma_act: Optional[torch.Tensor], B: torch.Tensor,
+                     pair_mask: Optional[torch.Tensor] = None, *, D_vv=None, e_pt2=None,
+                     pair_energy=None, pair_tnorm=None, want_pair_energy: bool = False,
+                     want_pair_tnorm: bool = False, workspace=None, stream=None) -> dict:
+    lib = _lib.load()
+    n_h = opts.n_core + opts.n_act
+    n_v, n_aux = opts.n_vir, opts.n_aux
+    _need(eps_hole, "eps_hole", torch.float64, n_h)
+    _need(eps_vir, "eps_vir", torch.float64, n_v)
+    _need(B, "B", torch.float64, n_h * n_v * n_aux)
+    if opts.n_act:
+        _need(gamma_act, "gamma_act", torch.float64, opts.n_act * opts.n_act)
+    else:
+        gamma_act = None
+    if pair_mask is not None:
+        _need(pair_mask, "pair_mask", torch.uint8, n_h * n_h)
+    dev = B.device
+    if D_vv is None:
+        D_vv = torch.empty((n_v, n_v), dtype=torch.float64, device=dev)
+    if e_pt2 is None:
+        e_pt2 = torch.empty(2, dtype=torch.float64, device=dev)
+    if pair_energy is None and want_pair_energy:
+        pair_energy = torch.empty((n_h, n_h), dtype=torch.float64, device=dev)
+    if pair_tnorm is None and want_pair_tnorm:
+        pair_tnorm = torch.empty((n_h, n_h), dtype=torch.float32, device=dev)
+    _need(D_vv, "D_vv", torch.float64, n_v * n_v)
+    _need(e_pt2, "e_pt2", torch.float64, 2)
+    if pair_energy is not None:
+        _need(pair_energy, "pair_energy", torch.float64, n_h * n_h)
+    if pair_tnorm is not None:
+        _need(pair_tnorm, "pair_tnorm", torch.float32, n_h * n_h)
+    nbytes = workspace_size(opts)
+    ws = _workspace(nbytes, dev, workspace)
+    check(lib.dfpt2_build_vv_density(ctypes.byref(opts), _ptr(eps_hole), _ptr(eps_vir), _ptr(gamma_act),
+                                     _ptr(B), _ptr(pair_mask), _ptr(D_vv), _ptr(e_pt2), _ptr(pair_energy),
+                                     _ptr(pair_tnorm), _ptr(ws), ctypes.c_size_t(ws.numel()),
+                                     _stream(stream)))
+    return dict(D_vv=D_vv, e_pt2=e_pt2, pair_energy=pair_energy, pair_tnorm=pair_tnorm)
+
+
+def fno_truncate_workspace_size(n_vir: int) -> int:
+    lib = _lib.load()
+    n = ctypes.c_size_t(0)
+    check(lib.fno_truncate_workspace_size(n_vir, ctypes.byref(n)))
+    return int(n.value)
+
+
+def fno_truncate(D_vv: torch.Tensor, p_o: float, degen_rel_tol: float = 0.0, *, occ=None, no_vecs=None,
+                 workspace=None, stream=None) -> dict:
+    lib = _lib.load()
+    n_v = D_vv.shape[0]
+    _need(D_vv, "D_vv", torch.float64, n_v * n_v)
+    dev = D_vv.device
+    if occ is None:
+        occ = torch.empty(n_v, dtype=torch.float64, device=dev)
+    if no_vecs is None:
+        no_vecs = torch.empty((n_v, n_v), dtype=torch.float64, device=dev)
+    _need(occ, "occ", torch.float64, n_v)
+    _need(no_vecs, "no_vecs", torch.float64, n_v * n_v)
+    ws = _workspace(fno_truncate_workspace_size(n_v), dev, workspace)
+    n_kept = ctypes.c_int64(0)
+    margins = (ctypes.c_double * 2)()
+    check(lib.fno_truncate(_ptr(D_vv), n_v, float(p_o), float(degen_rel_tol), _ptr(occ), _ptr(no_vecs),
+                           ctypes.byref(n_kept), margins, _ptr(ws), ctypes.c_size_t(ws.numel()),
+                           _stream(stream)))
+    return dict(occ=occ, no_vecs=no_vecs, n_kept=int(n_kept.value), margins=(margins[0], margins[1]))
+
+
+def eigh_sym(A: torch.Tensor, *, workspace=None, stream=None):
+    lib = _lib.load()
+    n = A.shape[0]
+    _need(A, "A", torch.float64, n * n)
+    w = torch.empty(n, dtype=torch.float64, device=A.device)
+    Z = torch.empty((n, n), dtype=torch.float64, device=A.device)
+    ws = _workspace(fno_truncate_workspace_size(n), A.device, workspace)
+    check(lib.dfpt2_eigh_sym(_ptr(A), n, _ptr(w), _ptr(Z), _ptr(ws), ctypes.c_size_t(ws.numel()),
+                             _stream(stream)))
+    return w, Z
+
+
+def pt2_correction_workspace_size(opts: Opts, n_kept: int) -> int:
+    lib = _lib.load()
+    n = ctypes.c_size_t(0)
+    check(lib.pt2_correction_workspace_size(ctypes.byref(opts), n_kept, ctypes.byref(n)))
+    return int(n.value)
+
+
+def pt2_energy_correction(opts: Opts, eps_hole, eps_vir, gamma_act, B, no_vecs, n_kept: int, e_full,
+                          *, workspace=None, stream=None) -> dict:
+    lib = _lib.load()
+    n_h = opts.n_core + opts.n_act
+    n_v, n_aux = opts.n_vir, opts.n_aux
+    _need(eps_hole, "eps_hole", torch.float64, n_h)
+    _need(eps_vir, "eps_vir", torch.float64, n_v)
+    _need(B, "B", torch.float64, n_h * n_v * n_aux)
+    _need(no_vecs, "no_vecs", torch.float64, n_v * n_v)
+    _need(e_full, "e_full", torch.float64, 2)
+    if opts.n_act:
+        _need(gamma_act, "gamma_act", torch.float64, opts.n_act * opts.n_act)
+    else:
+        gamma_act = None
+    dev = B.device
+    e_kept = torch.empty(2, dtype=torch.float64, device=dev)
+    corr = torch.empty(2, dtype=torch.float64, device=dev)
+    ws = _workspace(pt2_correction_workspace_size(opts, n_kept), dev, workspace)
+    check(lib.pt2_energy_correction(ctypes.byref(opts), _ptr(eps_hole), _ptr(eps_vir), _ptr(gamma_act), _ptr(B),
+                                    _ptr(no_vecs), int(n_kept), _ptr(e_full), _ptr(e_kept), _ptr(corr), _ptr(ws),
+                                    ctypes.c_size_t(ws.numel()), _stream(stream)))
+    return dict(e_kept=e_kept, correction=corr)
+
+
+def upload_inputs(inp, device="cuda") -> dict:
+    """Copy a synthetic input set (numpy, layout [hole][virtual][aux]) to the GPU."""
+    def t(x):
+        return torch.from_numpy(x).to(device=device, dtype=torch.float64).contiguous()
+    out = dict(eps_hole=t(inp.eps_hole), eps_vir=t(inp.eps_vir), B=t(inp.B))
+    out["gamma_act"] = t(inp.gamma_act.reshape(-1)) if inp.n_act else None
+    return out

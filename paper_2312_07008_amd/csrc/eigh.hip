@@ -1,0 +1,518 @@
+// FP64 symmetric eigensolver on the GPU, for the natural-orbital problem of
+// Eq. 8 (Gamma V = n V) and for the recanonicalization of the kept space.
+//
+//   1. Householder reduction to tridiagonal form, one column per step on the
+//      full symmetric matrix: a kernel that forms the reflector (redundantly in
+//      every workgroup) and p = tau A v, then a kernel for the rank-2 update
+//      A -= v w^T + w v^T with w = p - (tau/2)(p.v) v.
+//   2. Splitting at negligible off-diagonal entries, then every eigenvalue by
+//      bisection on Sturm counts (one thread per eigenvalue).
+//   3. Eigenvectors of the tridiagonal matrix by inverse iteration with a
+//      partially pivoted LU of T - lambda I; eigenvalues closer than a small
+//      multiple of ||T|| form a group that one thread handles in order,
+//      orthogonalizing every iterate against the group's earlier vectors.
+//   4. Back-transformation Z <- H_0 H_1 ... H_{n-3} Z, one workgroup per block
+//      of columns held in LDS, all reflectors applied in one launch.
+//   5. Columns sorted by eigenvalue and oriented so that the largest-magnitude
+//      component is positive.
+#include <cmath>
+#include <cfloat>
+
+#include "common.h"
+#include "eigh.h"
+
+namespace dfpt2 {
+
+namespace {
+
+__device__ inline double block_sum(double v, double* sh) {
+  // 256-thread workgroup sum; sh holds >= 4 doubles; ends with a barrier
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  double t = 0.0;
+  const int nw = blockDim.x >> 6;
+  for (int k = 0; k < nw; ++k) t += sh[k];
+  __syncthreads();
+  return t;
+}
+
+// ---------------------------------------------------------------- step a
+// Reflector of column k and p = tau A22 v, rows split over the grid.
+__global__ __launch_bounds__(256) void tridiag_step_a(const double* A, int n, int k, double* Vs,
+                                                      double* tau, double* d, double* e, double* p) {
+  extern __shared__ double vsh[];  // m doubles
+  __shared__ double red[8];
+  const int m = n - k - 1;
+  const double* rowk = A + (size_t)k * n + (k + 1);  // x_i = A[k][k+1+i] (symmetric)
+  double s2 = 0.0;
+  for (int i = 1 + threadIdx.x; i < m; i += blockDim.x) s2 += rowk[i] * rowk[i];
+  s2 = block_sum(s2, red);
+  const double alpha = rowk[0];
+  double t = 0.0, beta = alpha, scale = 0.0;
+  if (s2 > 0.0) {
+    const double mu = sqrt(alpha * alpha + s2);
+    beta = (alpha > 0.0) ? -mu : mu;
+    t = (beta - alpha) / beta;
+    scale = 1.0 / (alpha - beta);
+  }
+  for (int i = threadIdx.x; i < m; i += blockDim.x) vsh[i] = (i == 0) ? 1.0 : rowk[i] * scale;
+  __syncthreads();
+  if (blockIdx.x == 0) {
+    for (int i = threadIdx.x; i < m; i += blockDim.x) Vs[(size_t)k * n + i] = vsh[i];
+    if (threadIdx.x == 0) {
+      tau[k] = t;
+      e[k] = beta;
+      d[k] = A[(size_t)k * n + k];
+    }
+  }
+  const int lane = threadIdx.x & 63;
+  const int gw = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const int nwaves = gridDim.x * (blockDim.x >> 6);
+  for (int r = gw; r < m; r += nwaves) {
+    const double* row = A + (size_t)(k + 1 + r) * n + (k + 1);
+    double acc = 0.0;
+    for (int c = lane; c < m; c += 64) acc += row[c] * vsh[c];
+    acc = wave_sum(acc);
+    if (lane == 0) p[r] = t * acc;
+  }
+}
+
+// ---------------------------------------------------------------- step b
+// A22 -= v w^T + w v^T, w = p - (tau/2)(p.v) v.  grid.x over columns, grid.y over row bands.
+__global__ __launch_bounds__(256) void tridiag_step_b(double* A, int n, int k, const double* Vs,
+                                                      const double* tau, const double* p) {
+  __shared__ double red[8];
+  const int m = n - k - 1;
+  const double t = tau[k];
+  if (t == 0.0) return;
+  const double* v = Vs + (size_t)k * n;
+  double dot = 0.0;
+  for (int i = threadIdx.x; i < m; i += blockDim.x) dot += p[i] * v[i];
+  dot = block_sum(dot, red);
+  const double K = 0.5 * t * dot;
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= m) return;
+  const double vc = v[c];
+  const double wc = p[c] - K * vc;
+  const int rows_per = (m + gridDim.y - 1) / gridDim.y;
+  const int r0 = blockIdx.y * rows_per;
+  const int r1 = min(m, r0 + rows_per);
+  for (int r = r0; r < r1; ++r) {
+    const double vr = v[r];
+    const double wr = p[r] - K * vr;
+    double* a = A + (size_t)(k + 1 + r) * n + (k + 1 + c);
+    *a -= vr * wc + wr * vc;
+  }
+}
+
+__global__ void tridiag_tail(const double* A, int n, double* d, double* e) {
+  if (threadIdx.x != 0) return;
+  if (n >= 2) {
+    d[n - 2] = A[(size_t)(n - 2) * n + (n - 2)];
+    d[n - 1] = A[(size_t)(n - 1) * n + (n - 1)];
+    e[n - 2] = A[(size_t)(n - 1) * n + (n - 2)];
+  } else {
+    d[0] = A[0];
+  }
+}
+
+// ---------------------------------------------------------------- splitting
+// Zero negligible off-diagonals, record unreduced blocks: blk_of[pos] = start of
+// the block containing pos; blk_end[pos] = one past its end.  Also the norm.
+__global__ void tridiag_split(int n, const double* d, double* e, int* blk_start, int* blk_end,
+                              double* tnorm) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double nrm = 0.0;
+  for (int i = 0; i < n; ++i) {
+    double r = fabs(d[i]) + (i > 0 ? fabs(e[i - 1]) : 0.0) + (i + 1 < n ? fabs(e[i]) : 0.0);
+    nrm = fmax(nrm, r);
+  }
+  *tnorm = nrm;
+  const double eps = DBL_EPSILON;
+  int start = 0;
+  for (int i = 0; i < n; ++i) {
+    bool brk = (i == n - 1);
+    if (!brk) {
+      const double ee = fabs(e[i]);
+      if (ee <= eps * sqrt(fabs(d[i])) * sqrt(fabs(d[i + 1])) || ee <= DBL_MIN * 1e6 || ee <= 1e-300) {
+        e[i] = 0.0;
+        brk = true;
+      }
+    }
+    if (brk) {
+      for (int q = start; q <= i; ++q) {
+        blk_start[q] = start;
+        blk_end[q] = i + 1;
+      }
+      start = i + 1;
+    }
+  }
+}
+
+// Number of eigenvalues of the block [s, t) smaller than x (Sturm sequence).
+__device__ int sturm_count(const double* d, const double* e, int s, int t, double x, double pivmin) {
+  int cnt = 0;
+  double q = d[s] - x;
+  if (fabs(q) < pivmin) q = -pivmin;
+  if (q < 0.0) ++cnt;
+  for (int i = s + 1; i < t; ++i) {
+    q = d[i] - x - e[i - 1] * e[i - 1] / q;
+    if (fabs(q) < pivmin) q = -pivmin;
+    if (q < 0.0) ++cnt;
+  }
+  return cnt;
+}
+
+// Thread g: the (g - start)-th eigenvalue of the block containing position g.
+__global__ void tridiag_bisect(int n, const double* d, const double* e, const int* blk_start,
+                               const int* blk_end, const double* tnorm, double* lam) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n) return;
+  const int s = blk_start[g], t = blk_end[g], j = g - s;
+  double lo = DBL_MAX, hi = -DBL_MAX;
+  for (int i = s; i < t; ++i) {
+    const double r = (i > s ? fabs(e[i - 1]) : 0.0) + (i + 1 < t ? fabs(e[i]) : 0.0);
+    lo = fmin(lo, d[i] - r);
+    hi = fmax(hi, d[i] + r);
+  }
+  const double nrm = fmax(*tnorm, DBL_MIN);
+  const double pivmin = DBL_MIN * fmax(1.0, nrm * nrm) * 4.0;
+  const double pad = 2.0 * DBL_EPSILON * nrm * (t - s) + 2.0 * pivmin;
+  lo -= pad;
+  hi += pad;
+  // invariant: count(lo) <= j < count(hi)
+  for (int it = 0; it < 200; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (mid <= lo || mid >= hi) break;
+    if (hi - lo <= 2.0 * DBL_EPSILON * fmax(fabs(lo), fabs(hi)) + pivmin) break;
+    if (sturm_count(d, e, s, t, mid, pivmin) > j) hi = mid;
+    else lo = mid;
+  }
+  lam[g] = 0.5 * (lo + hi);
+}
+
+// ------------------------------------------------------------ inverse iteration
+struct LuCols {
+  double *u1, *u2, *u3, *l, *piv;  // [pos][n] layout, column g owned by thread g
+};
+
+__device__ inline double hash_unit(unsigned a, unsigned b) {
+  unsigned h = a * 2654435761u ^ (b + 0x9e3779b9u + (a << 6) + (a >> 2));
+  h ^= h >> 16;
+  h *= 0x7feb352du;
+  h ^= h >> 15;
+  h *= 0x846ca68bu;
+  h ^= h >> 16;
+  return ((double)(h & 0xffffff) / 16777216.0) - 0.5;
+}
+
+// Factor T_b - lam I (block [s, t)) into column g of the LU arrays.
+__device__ void lu_factor(const double* d, const double* e, int s, int t, double lam, double tiny,
+                          const LuCols& L, int n, int g) {
+  double alpha = d[s] - lam;
+  double beta = (s + 1 < t) ? e[s] : 0.0;
+  for (int i = s; i < t - 1; ++i) {
+    const double c = e[i];
+    const double an = d[i + 1] - lam;
+    const double bn = (i + 2 < t) ? e[i + 1] : 0.0;
+    const size_t o = (size_t)i * n + g;
+    if (fabs(alpha) >= fabs(c)) {
+      double a_ = alpha;
+      if (a_ == 0.0) a_ = tiny;
+      const double mlt = c / a_;
+      L.u1[o] = a_;
+      L.u2[o] = beta;
+      L.u3[o] = 0.0;
+      L.l[o] = mlt;
+      L.piv[o] = 0.0;
+      alpha = an - mlt * beta;
+      beta = bn;
+    } else {
+      const double mlt = alpha / c;
+      L.u1[o] = c;
+      L.u2[o] = an;
+      L.u3[o] = bn;
+      L.l[o] = mlt;
+      L.piv[o] = 1.0;
+      alpha = beta - mlt * an;
+      beta = -mlt * bn;
+    }
+  }
+  const size_t o = (size_t)(t - 1) * n + g;
+  L.u1[o] = (alpha == 0.0) ? tiny : alpha;
+  L.u2[o] = 0.0;
+  L.u3[o] = 0.0;
+}
+
+// Solve in place: x (column g of X over positions [s, t)) <- (T - lam I)^{-1} x.
+__device__ void lu_solve(int s, int t, const LuCols& L, int n, int g, double* X, int xcol) {
+  for (int i = s; i < t - 1; ++i) {
+    const size_t o = (size_t)i * n + g;
+    double yi = X[(size_t)i * n + xcol], yn = X[(size_t)(i + 1) * n + xcol];
+    if (L.piv[o] != 0.0) {
+      const double tmp = yi;
+      yi = yn;
+      yn = tmp;
+    }
+    yn -= L.l[o] * yi;
+    X[(size_t)i * n + xcol] = yi;
+    X[(size_t)(i + 1) * n + xcol] = yn;
+  }
+  for (int i = t - 1; i >= s; --i) {
+    const size_t o = (size_t)i * n + g;
+    double v = X[(size_t)i * n + xcol];
+    if (i + 1 < t) v -= L.u2[o] * X[(size_t)(i + 1) * n + xcol];
+    if (i + 2 < t) v -= L.u3[o] * X[(size_t)(i + 2) * n + xcol];
+    X[(size_t)i * n + xcol] = v / L.u1[o];
+  }
+}
+
+// Group leaders (first eigenvalue of a near-degenerate run inside a block) compute
+// the vectors of their whole group; X is row-major n x n, column g = vector g.
+__global__ void tridiag_inverse_iteration(int n, const double* d, const double* e, const int* blk_start,
+                                          const int* blk_end, const double* tnorm, const double* lam,
+                                          LuCols L, double* X, int* status) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n) return;
+  const int s = blk_start[g], t = blk_end[g];
+  const double nrm = fmax(*tnorm, DBL_MIN);
+  const double grp_tol = 1e-10 * nrm;
+  // leader test: previous eigenvalue in the same block is not within grp_tol
+  if (g > s && fabs(lam[g] - lam[g - 1]) <= grp_tol) return;
+  int g1 = g + 1;
+  while (g1 < t && fabs(lam[g1] - lam[g1 - 1]) <= grp_tol) ++g1;
+  const double tiny = DBL_EPSILON * nrm;
+  for (int q = g; q < g1; ++q) {
+    // zero the column outside the block, random start inside
+    for (int i = 0; i < n; ++i) X[(size_t)i * n + q] = (i >= s && i < t) ? hash_unit(q, i) : 0.0;
+    // eigenvalues of a group are spread by a few ulps so that the factors differ
+    const double lq = lam[q] + (double)(q - g) * 4.0 * DBL_EPSILON * nrm;
+    lu_factor(d, e, s, t, lq, tiny, L, n, g);
+    double nx = 0.0;
+    for (int it = 0; it < 4; ++it) {
+      lu_solve(s, t, L, n, g, X, q);
+      // orthogonalize against earlier vectors of the group (twice for stability)
+      for (int pass = 0; pass < 2; ++pass) {
+        for (int r = g; r < q; ++r) {
+          double dp = 0.0;
+          for (int i = s; i < t; ++i) dp += X[(size_t)i * n + r] * X[(size_t)i * n + q];
+          for (int i = s; i < t; ++i) X[(size_t)i * n + q] -= dp * X[(size_t)i * n + r];
+        }
+      }
+      nx = 0.0;
+      for (int i = s; i < t; ++i) nx += X[(size_t)i * n + q] * X[(size_t)i * n + q];
+      nx = sqrt(nx);
+      if (!(nx > 0.0) || !isfinite(nx)) {
+        atomicExch(status, 1);
+        return;
+      }
+      const double inv = 1.0 / nx;
+      for (int i = s; i < t; ++i) X[(size_t)i * n + q] *= inv;
+    }
+  }
+}
+
+// ------------------------------------------------------------ back-transform
+// Z <- H_0 ... H_{n-3} Z for a block of `cw` columns held in LDS.
+__global__ __launch_bounds__(256) void tridiag_backtransform(int n, const double* Vs, const double* tau,
+                                                             double* Z, int cw) {
+  extern __shared__ double zs[];  // [n][cw]
+  __shared__ double part[4][8];
+  const int c0 = blockIdx.x * cw;
+  const int ncol = min(cw, n - c0);
+  for (int idx = threadIdx.x; idx < n * cw; idx += blockDim.x) {
+    const int r = idx / cw, c = idx % cw;
+    zs[idx] = (c < ncol) ? Z[(size_t)r * n + c0 + c] : 0.0;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int k = n - 3; k >= 0; --k) {
+    const double t = tau[k];
+    if (t == 0.0) continue;
+    const int m = n - k - 1;
+    const double* v = Vs + (size_t)k * n;
+    double acc[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) acc[c] = 0.0;
+    for (int i = threadIdx.x; i < m; i += blockDim.x) {
+      const double vi = v[i];
+      const double* zr = zs + (size_t)(k + 1 + i) * cw;
+#pragma unroll
+      for (int c = 0; c < 8; ++c)
+        if (c < cw) acc[c] += vi * zr[c];
+    }
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      if (c < cw) {
+        double sv = wave_sum(acc[c]);
+        if (lane == 0) part[w][c] = sv;
+      }
+    }
+    __syncthreads();
+    double sc[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) sc[c] = (c < cw) ? t * ((part[0][c] + part[1][c]) + (part[2][c] + part[3][c])) : 0.0;
+    for (int i = threadIdx.x; i < m; i += blockDim.x) {
+      const double vi = v[i];
+      double* zr = zs + (size_t)(k + 1 + i) * cw;
+#pragma unroll
+      for (int c = 0; c < 8; ++c)
+        if (c < cw) zr[c] -= vi * sc[c];
+    }
+    __syncthreads();
+  }
+  for (int idx = threadIdx.x; idx < n * cw; idx += blockDim.x) {
+    const int r = idx / cw, c = idx % cw;
+    if (c < ncol) Z[(size_t)r * n + c0 + c] = zs[idx];
+  }
+}
+
+// ------------------------------------------------------------ sort + orient
+// rank of eigenvalue g among all (ties by index), ascending
+__global__ void eig_rank(int n, const double* lam, int* rank) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n) return;
+  const double x = lam[g];
+  int r = 0;
+  for (int q = 0; q < n; ++q) {
+    const double y = lam[q];
+    r += (y < x || (y == x && q < g)) ? 1 : 0;
+  }
+  rank[g] = r;
+}
+
+// out column dst(g) = sign-oriented column g; descending: dst = n-1-rank
+__global__ void eig_permute(int n, const double* lam, const int* rank, const double* Zin, double* w_out,
+                            double* Z_out, int descending) {
+  const int g = blockIdx.x;
+  __shared__ double bestv[4];
+  __shared__ int besti[4];
+  double bv = -1.0;
+  int bi = 0x7fffffff;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const double a = fabs(Zin[(size_t)i * n + g]);
+    if (a > bv || (a == bv && i < bi)) {
+      bv = a;
+      bi = i;
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    const double ov = __shfl_xor(bv, off, 64);
+    const int oi = __shfl_xor(bi, off, 64);
+    if (ov > bv || (ov == bv && oi < bi)) {
+      bv = ov;
+      bi = oi;
+    }
+  }
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) {
+    bestv[w] = bv;
+    besti[w] = bi;
+  }
+  __syncthreads();
+  bv = bestv[0];
+  bi = besti[0];
+  for (int q = 1; q < (int)(blockDim.x >> 6); ++q)
+    if (bestv[q] > bv || (bestv[q] == bv && besti[q] < bi)) {
+      bv = bestv[q];
+      bi = besti[q];
+    }
+  const double sgn = (Zin[(size_t)bi * n + g] < 0.0) ? -1.0 : 1.0;
+  const int dst = descending ? (n - 1 - rank[g]) : rank[g];
+  if (threadIdx.x == 0) w_out[dst] = lam[g];
+  for (int i = threadIdx.x; i < n; i += blockDim.x) Z_out[(size_t)i * n + dst] = sgn * Zin[(size_t)i * n + g];
+}
+
+__global__ void zero_int(int* p, int n) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0;
+}
+
+}  // namespace
+
+size_t eigh_workspace_bytes(int n) {
+  const size_t nn = (size_t)n * n;
+  size_t b = 0;
+  auto add = [&](size_t x) { b += align_up(x, 256); };
+  add(nn * 8);      // A work copy
+  add(nn * 8);      // reflectors
+  add(nn * 8);      // X (tridiagonal eigenvectors, then back-transformed)
+  add(5 * nn * 8);  // LU columns
+  add((size_t)n * 8 * 5);  // tau d e p lam
+  add((size_t)n * 4 * 3 + 64);  // blk_start blk_end rank status
+  add(64);          // tnorm
+  return b;
+}
+
+int eigh_run(const double* A_in, int n, double* w_out, double* Z_out, char* ws, size_t ws_bytes, hipStream_t st,
+             int descending) {
+  if (n < 1 || n > kEighMaxN) return fail(DFPT2_ERR_INVALID_ARG, "eigh: n=%d outside [1, %d]", n, kEighMaxN);
+  if (ws_bytes < eigh_workspace_bytes(n)) return fail(DFPT2_ERR_WORKSPACE, "eigh workspace too small");
+  const size_t nn = (size_t)n * n;
+  size_t off = 0;
+  auto take = [&](size_t x) {
+    char* p = ws + off;
+    off += align_up(x, 256);
+    return p;
+  };
+  double* A = (double*)take(nn * 8);
+  double* Vs = (double*)take(nn * 8);
+  double* X = (double*)take(nn * 8);
+  double* lu = (double*)take(5 * nn * 8);
+  double* tau = (double*)take((size_t)n * 8 * 5);
+  double* d = tau + n;
+  double* e = d + n;
+  double* p = e + n;
+  double* lam = p + n;
+  int* blk_start = (int*)take((size_t)n * 4 * 3 + 64);
+  int* blk_end = blk_start + n;
+  int* rank = blk_end + n;
+  int* status = rank + n;
+  double* tnorm = (double*)take(64);
+  hipError_t err;
+  if ((err = hipMemcpyAsync(A, A_in, nn * 8, hipMemcpyDeviceToDevice, st)) != hipSuccess)
+    return hip_fail(err, "eigh copy");
+  hipLaunchKernelGGL(zero_int, dim3(1), dim3(64), 0, st, status, 1);
+  // 1. tridiagonalization
+  for (int k = 0; k + 2 < n; ++k) {
+    const int m = n - k - 1;
+    int ga = (m + 3) / 4;
+    if (ga > 512) ga = 512;
+    hipLaunchKernelGGL(tridiag_step_a, dim3(ga), dim3(256), (size_t)m * 8, st, A, n, k, Vs, tau, d, e, p);
+    int gx = (m + 255) / 256;
+    int gy = (m + 15) / 16;
+    if (gy > 256) gy = 256;
+    hipLaunchKernelGGL(tridiag_step_b, dim3(gx, gy), dim3(256), 0, st, A, n, k, Vs, tau, p);
+  }
+  hipLaunchKernelGGL(tridiag_tail, dim3(1), dim3(64), 0, st, A, n, d, e);
+  // 2. split + bisection
+  hipLaunchKernelGGL(tridiag_split, dim3(1), dim3(64), 0, st, n, d, e, blk_start, blk_end, tnorm);
+  hipLaunchKernelGGL(tridiag_bisect, dim3((n + 127) / 128), dim3(128), 0, st, n, d, e, blk_start, blk_end, tnorm,
+                     lam);
+  // 3. inverse iteration
+  LuCols L{lu, lu + nn, lu + 2 * nn, lu + 3 * nn, lu + 4 * nn};
+  hipLaunchKernelGGL(tridiag_inverse_iteration, dim3((n + 63) / 64), dim3(64), 0, st, n, d, e, blk_start, blk_end,
+                     tnorm, lam, L, X, status);
+  // 4. back-transformation
+  if (n > 2) {
+    int cw = 8;
+    while (cw > 1 && (size_t)n * cw * 8 > 150 * 1024) cw >>= 1;
+    if ((size_t)n * cw * 8 > 150 * 1024) return fail(DFPT2_ERR_UNSUPPORTED, "eigh: n=%d too large", n);
+    hipLaunchKernelGGL(tridiag_backtransform, dim3((n + cw - 1) / cw), dim3(256), (size_t)n * cw * 8, st, n, Vs,
+                       tau, X, cw);
+  }
+  // 5. sort + orient
+  hipLaunchKernelGGL(eig_rank, dim3((n + 255) / 256), dim3(256), 0, st, n, lam, rank);
+  hipLaunchKernelGGL(eig_permute, dim3(n), dim3(256), 0, st, n, lam, rank, X, w_out, Z_out, descending);
+  if ((err = hipGetLastError()) != hipSuccess) return hip_fail(err, "eigh launch");
+  int hs = 0;
+  if ((err = hipMemcpyAsync(&hs, status, sizeof(int), hipMemcpyDeviceToHost, st)) != hipSuccess)
+    return hip_fail(err, "eigh status copy");
+  if ((err = hipStreamSynchronize(st)) != hipSuccess) return hip_fail(err, "eigh sync");
+  if (hs != 0) return fail(DFPT2_ERR_NOT_CONVERGED, "inverse iteration produced a zero or non-finite vector");
+  return DFPT2_OK;
+}
+
+}  // namespace dfpt2

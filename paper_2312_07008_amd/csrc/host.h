@@ -1,0 +1,39 @@
+// Host-side plan of one pass and internal entry points (not exported).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+#include "../../include/dfpt2.h"
+
+namespace dfpt2 {
+
+extern thread_local std::string g_last_error;
+int fail(int status, const char* fmt, ...);
+int hip_fail(hipError_t e, const char* what);
+size_t align_up(size_t x, size_t a);
+
+struct PassPlan {
+  int n_core, n_act, n_h, n_v, n_aux;
+  int nt, nTP;      // 64-wide virtual tiles and upper-triangle tile pairs
+  int n_up;         // unordered core-core pairs
+  int batch;        // unordered pairs per batch
+  int nsplit;       // density split slices
+  double w_density; // density weight of one ordered closed-shell pair
+  size_t off_pairs, off_count, off_T, off_epart, off_tpart, off_pe, off_tn2, off_Dpart;
+  size_t ws_bytes;
+};
+
+int plan_pass(const dfpt2_opts* o, PassPlan* pl);
+
+int run_pass_fp64(const PassPlan& pl, const dfpt2_opts& o, const double* eps_h, const double* eps_v,
+                  const double* B, const uint8_t* mask, double* D, double* e_out, double* pair_energy,
+                  float* pair_tnorm, char* ws, hipStream_t s);
+
+hipError_t gemm_f64(const double* A, int lda, long long sA, int transA, const double* B, int ldb, long long sB,
+                    int transB, double* C, int ldc, long long sC, int M, int N, int K, int batch, double alpha,
+                    double beta, hipStream_t st);
+
+}  // namespace dfpt2

@@ -1,0 +1,49 @@
+// Kernel launch interfaces used by the host library (internal).
+#pragma once
+#include "common.h"
+
+namespace dfpt2 {
+
+// ---------------------------------------------------------------- pair kernel
+struct PairKernelArgs {
+  const double* B;      // [n_h][n_v][n_aux]
+  const double* eps_h;  // [n_h]
+  const double* eps_v;  // [n_v]
+  const int2* pairs;    // [n_pairs] unordered (i <= j)
+  double* T;            // [n_pairs][n_v][n_v] amplitudes out, or null
+  double* Vr;           // [n_pairs][n_v][n_v] renormalized integrals out, or null
+  double* epart;        // [n_pairs][nTP] energy partial per tile pair, or null
+  double* tpart;        // [n_pairs][nTP] ||T||^2 partial per tile pair, or null
+  int n_v, n_aux, nt, nTP;
+  double s;
+  double e_weight;      // energy weight of one ordered pair
+};
+hipError_t launch_pair_gemm_f64(const PairKernelArgs& a, int n_pairs, hipStream_t st);
+
+// ------------------------------------------------------------- density kernel
+struct DensityKernelArgs {
+  const double* T;      // [n_pairs][n_v][n_v] full amplitude matrices of unordered pairs
+  const double* pw;     // [n_pairs] per-pair weight, or null (then w for every pair)
+  const int2* pairs;    // [n_pairs]
+  double* Dpart;        // [nsplit][n_v][n_v]
+  int n_v, nt, nTP, n_pairs, nsplit;
+  double w;             // weight of one ordered pair (closed shell, spin-summed: 2)
+  int accumulate;       // add into Dpart instead of overwriting
+};
+hipError_t launch_density_f64(const DensityKernelArgs& a, hipStream_t st);
+hipError_t launch_density_reduce(const double* Dpart, int nsplit, int n_v, double* D, hipStream_t st);
+
+// ------------------------------------------------------------ small kernels
+hipError_t launch_fill(double* p, size_t n, double v, hipStream_t st);
+hipError_t launch_fill_f32(float* p, size_t n, float v, hipStream_t st);
+hipError_t launch_build_pairs(const uint8_t* mask, int n_core, int n_h, int2* pairs, int* count,
+                              hipStream_t st);
+// per-pair reduction of tile partials into double-double pair energies and ||T||^2
+hipError_t launch_pair_reduce(const double* epart, const double* tpart, int nTP, int n_pairs,
+                              double* pe /*[n][2]*/, double* tn2 /*[n]*/, hipStream_t st);
+// sum of pair energies (double-double) -> e[2]; optional scatter to n_h x n_h outputs
+hipError_t launch_energy_finalize(const double* pe, const double* tn2, const int2* pairs,
+                                  const int* count, int max_pairs, int n_h, double* e_out,
+                                  double* pair_energy, float* pair_tnorm, hipStream_t st);
+
+}  // namespace dfpt2

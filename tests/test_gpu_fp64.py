@@ -1,0 +1,161 @@
+"""GPU parity of the FP64 HIP path against the FP64 CPU oracle (through the C ABI).
+
+Bars: energy within 1e-8 Eh (double-double on both sides), density and
+occupation numbers within a few ulps of their magnitude, kept counts exact.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import dsrg_pt2 as o
+from gpu_common import dd_diff, gpu_pass, need_gpu, torch
+
+pytestmark = pytest.mark.gpu
+
+E_TOL = 1e-8
+
+
+def _closed(n_occ, n_vir, n_aux, seed):
+    return synth.generate(n_occ, 0, n_vir, n_aux, seed)
+
+
+CASES = [
+    ("c1", None, 0.5),
+    ("ragged_odd", (7, 0, 131, 77), 0.5),      # odd n_v and n_aux: scalar load paths, ragged tiles
+    ("tiles_ragged", (12, 0, 200, 256), 1.0),  # several tiles + ragged tail
+    ("one_hole", (1, 0, 70, 33), 0.8),          # single pair, symmetric amplitudes
+]
+
+
+@pytest.mark.parametrize("name,sizes,s", CASES, ids=[c[0] for c in CASES])
+def test_pass_energy_density_parity(name, sizes, s):
+    inp = synth.config_inputs("c1") if sizes is None else synth.generate(*sizes, seed=3)
+    print(f"case {name} sizes={sizes} s={s}", flush=True)
+    ref = o.pt2_pass_inputs(inp, s)
+    g = gpu_pass(inp, s)
+    assert dd_diff(g["energy"], ref.energy) <= E_TOL
+    scale = np.abs(ref.D_vv).max()
+    assert np.abs(g["D"] - ref.D_vv).max() <= 1e-12 * scale
+    assert np.array_equal(g["D"], g["D"].T)
+    np.testing.assert_allclose(g["pair_energy"], ref.pair_energy, rtol=1e-11, atol=1e-14)
+    np.testing.assert_allclose(g["pair_tnorm"], ref.pair_tnorm, rtol=1e-6)
+
+
+def test_pass_is_bitwise_reproducible():
+    inp = synth.generate(9, 0, 150, 120, seed=5)
+    a = gpu_pass(inp, 0.5)
+    b = gpu_pass(inp, 0.5)
+    assert a["energy"] == b["energy"]
+    assert np.array_equal(a["D"], b["D"])
+
+
+def test_pair_mask_drops_pairs():
+    inp = synth.generate(8, 0, 90, 64, seed=7)
+    rng = np.random.default_rng(1)
+    m = rng.random((8, 8)) < 0.6
+    m = np.triu(m) | np.triu(m).T
+    ref = o.pt2_pass_inputs(inp, 0.5, pair_mask=m)
+    g = gpu_pass(inp, 0.5, pair_mask=m)
+    assert dd_diff(g["energy"], ref.energy) <= E_TOL
+    assert np.abs(g["D"] - ref.D_vv).max() <= 1e-12 * np.abs(ref.D_vv).max()
+    # an all-zero mask gives an exactly zero pass
+    z = gpu_pass(inp, 0.5, pair_mask=np.zeros((8, 8), bool))
+    assert z["E"] == 0.0 and not z["D"].any()
+
+
+def test_small_batches_match_one_batch():
+    inp = synth.generate(10, 0, 96, 80, seed=8)
+    a = gpu_pass(inp, 0.7, pair_batch=3)
+    b = gpu_pass(inp, 0.7)
+    assert dd_diff(a["energy"], b["energy"]) <= 1e-12
+    assert np.abs(a["D"] - b["D"]).max() <= 1e-13 * np.abs(b["D"]).max()
+
+
+def test_density_convention_per_spin_is_half():
+    inp = synth.generate(4, 0, 64, 40, seed=2)
+    a = gpu_pass(inp, 0.5)
+    b = gpu_pass(inp, 0.5, density_convention=1)
+    np.testing.assert_array_equal(b["D"] * 2.0, a["D"])
+
+
+# ------------------------------------------------------------------ eigensolver
+
+def _gpu_eigh(A):
+    dp = need_gpu()
+    w, Z = dp.eigh_sym(torch.from_numpy(np.ascontiguousarray(A)).cuda())
+    torch.cuda.synchronize()
+    return w.cpu().numpy(), Z.cpu().numpy()
+
+
+@pytest.mark.parametrize("kind,n", [("random", 1), ("random", 2), ("random", 3), ("random", 97),
+                                    ("random", 256), ("identity", 40), ("diag_repeat", 33),
+                                    ("blocks", 60), ("psd_lowrank", 120), ("clustered", 80)])
+def test_eigh_against_lapack(kind, n):
+    rng = np.random.default_rng(n)
+    if kind == "random":
+        X = rng.standard_normal((n, n))
+        A = X + X.T
+    elif kind == "identity":
+        A = np.eye(n) * 3.0
+    elif kind == "diag_repeat":
+        A = np.diag(np.repeat([1.0, -2.0, 5.0], n // 3 + 1)[:n])
+    elif kind == "blocks":
+        A = np.zeros((n, n))
+        for s0 in range(0, n, 15):
+            X = rng.standard_normal((15, 15))
+            A[s0:s0 + 15, s0:s0 + 15] = X @ X.T
+    elif kind == "psd_lowrank":
+        X = rng.standard_normal((n, 7))
+        A = X @ X.T
+    else:  # clustered: eigenvalues 1 +- 1e-12 * k
+        Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+        lam = np.concatenate([1.0 + 1e-12 * np.arange(n // 2), 5.0 + rng.random(n - n // 2)])
+        A = (Q * lam) @ Q.T
+        A = 0.5 * (A + A.T)
+    w, Z = _gpu_eigh(A)
+    wref = np.linalg.eigvalsh(A)
+    nrm = max(np.abs(wref).max(), 1e-300)
+    assert np.all(np.diff(w) >= 0)
+    assert np.abs(w - wref).max() <= 1e-13 * nrm * max(1.0, np.sqrt(n) / 4)
+    assert np.abs(A @ Z - Z * w[None, :]).max() <= 1e-12 * nrm * max(1.0, np.sqrt(n) / 4)
+    assert np.abs(Z.T @ Z - np.eye(n)).max() <= 1e-11
+
+
+# ------------------------------------------------------------------ truncation + correction
+
+@pytest.mark.parametrize("p_o", [0.98, 0.985, 0.99, 1.0])
+def test_fno_truncate_and_correction_c1(p_o):
+    dp = need_gpu()
+    inp = synth.config_inputs("c1")
+    ref = o.full_pipeline(inp, 0.5, p_o)
+    g = gpu_pass(inp, 0.5)
+    t = dp.fno_truncate(g["raw"]["D_vv"], p_o)
+    occ = t["occ"].cpu().numpy()
+    vec = t["no_vecs"].cpu().numpy()
+    assert t["n_kept"] == ref["n_kept"]
+    assert np.abs(occ - ref["occ"]).max() <= 1e-12 * ref["occ"].max()
+    assert abs(t["margins"][0] - ref["margins"][0]) < 1e-10 and abs(t["margins"][1] - ref["margins"][1]) < 1e-10
+    assert np.abs(vec - ref["no_vecs"]).max() <= 1e-8
+    d = g["dev"]
+    c = dp.pt2_energy_correction(g["opts"], d["eps_hole"], d["eps_vir"], d["gamma_act"], d["B"], t["no_vecs"],
+                                 t["n_kept"], g["raw"]["e_pt2"])
+    ek = c["e_kept"].cpu().numpy()
+    cc = c["correction"].cpu().numpy()
+    assert dd_diff((ek[0], ek[1]), ref["e_kept"]) <= E_TOL
+    assert dd_diff((cc[0], cc[1]), ref["correction"]) <= E_TOL
+    if p_o == 1.0:
+        assert abs(cc[0] + cc[1]) <= 1e-11 * abs(ref["energy"][0])
+
+
+def test_fno_near_degeneracy_widening():
+    dp = need_gpu()
+    occ = np.array([5.0, 2.0, 1.995, 1.985, 1.97, 1.0])
+    rng = np.random.default_rng(0)
+    Q, _ = np.linalg.qr(rng.standard_normal((6, 6)))
+    D = (Q * occ) @ Q.T
+    D = 0.5 * (D + D.T)
+    p_o = 6.99 / occ.sum()          # strictly inside the gap, away from a zero margin
+    t0 = dp.fno_truncate(torch.from_numpy(D).cuda(), p_o, 0.0)
+    t1 = dp.fno_truncate(torch.from_numpy(D).cuda(), p_o, 0.01)
+    assert t0["n_kept"] == o.expand_near_degenerate(occ, o.kept_count_po(occ, p_o)[0], 0.0)
+    assert t1["n_kept"] == o.expand_near_degenerate(occ, o.kept_count_po(occ, p_o)[0], 0.01)
