@@ -164,6 +164,30 @@ int pt2_energy_correction(const dfpt2_opts* opts, const double* eps_hole, const 
                           double* correction, void* workspace, size_t ws_bytes,
                           dfpt2_stream_t stream);
 
+/*
+ * Stage timers for measurement (not part of the method).  When enabled, every
+ * entry point brackets its kernel launches with HIP events on the stream it was
+ * given and, at its next stream synchronization, adds the elapsed GPU time to
+ * the stage counters below.  Counters are process-global; enable and read them
+ * from one host thread.  dfpt2_profile_enable(1) also resets them.
+ *   ms        host out [DFPT2_NSTAGE], accumulated milliseconds per stage
+ *   launches  host out [DFPT2_NSTAGE], number of timed launches per stage
+ */
+enum {
+  DFPT2_STAGE_PAIR = 0,       /* pair kernel: V = B_i B_j^T + regularizer/energy epilogue */
+  DFPT2_STAGE_DENSITY = 1,    /* density kernel (D_vv accumulation) */
+  DFPT2_STAGE_SPLIT = 2,      /* operand splitting into BF16/FP8 slices */
+  DFPT2_STAGE_REDUCE = 3,     /* pair lists, reductions, finalization */
+  DFPT2_STAGE_ACTIVE = 4,     /* active-index rotation and active-pair energy */
+  DFPT2_STAGE_EIGH = 5,       /* symmetric eigensolver */
+  DFPT2_STAGE_TRANSFORM = 6,  /* recanonicalization GEMMs and B transform */
+  DFPT2_STAGE_KEPT_PAIR = 7,  /* pair kernel of the kept-space energy */
+  DFPT2_STAGE_SCREEN = 8,     /* pair features, MLP, mask compaction */
+  DFPT2_NSTAGE = 9
+};
+int dfpt2_profile_enable(int on);
+int dfpt2_profile_read(double* ms, int64_t* launches);
+
 #ifdef __cplusplus
 }
 #endif

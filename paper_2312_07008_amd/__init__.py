@@ -6,5 +6,6 @@ tensors into its entry points; there is no CPU fallback.
 """
 from ._lib import (BF16_SLICED, FP8_SLICED, FP64, DfptError, Opts, LIB_PATH, load)  # noqa: F401
 from .api import (build_vv_density, eigh_sym, fno_truncate, fno_truncate_workspace_size,  # noqa: F401
-                  make_opts, pt2_correction_workspace_size, pt2_energy_correction, upload_inputs,
+                  make_opts, profile_enable, profile_read, pt2_correction_workspace_size,
+                  pt2_energy_correction, upload_inputs,
                   workspace_size)

@@ -62,7 +62,11 @@ SIGNATURES = {
     "pt2_correction_workspace_size": (_int, [ctypes.POINTER(Opts), _i64, ctypes.POINTER(_sz)]),
     "pt2_energy_correction": (_int, [ctypes.POINTER(Opts), _vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp,
                                      _vp, _sz, _vp]),
+    "dfpt2_profile_enable": (_int, [_int]),
+    "dfpt2_profile_read": (_int, [ctypes.POINTER(_dbl), ctypes.POINTER(_i64)]),
 }
+
+STAGES = ["pair", "density", "split", "reduce", "active", "eigh", "transform", "kept_pair", "screen"]
 
 _lib = None
 

@@ -17,7 +17,7 @@ from ._lib import Opts, check
 
 __all__ = ["make_opts", "workspace_size", "build_vv_density", "fno_truncate_workspace_size",
            "fno_truncate", "eigh_sym", "pt2_correction_workspace_size", "pt2_energy_correction",
-           "upload_inputs"]
+           "upload_inputs", "profile_enable", "profile_read"]
 
 
 def _ptr(t: Optional[torch.Tensor]):
@@ -184,3 +184,17 @@ def upload_inputs(inp, device="cuda") -> dict:
     out = dict(eps_hole=t(inp.eps_hole), eps_vir=t(inp.eps_vir), B=t(inp.B))
     out["gamma_act"] = t(inp.gamma_act.reshape(-1)) if inp.n_act else None
     return out
+
+
+def profile_enable(on: bool = True) -> None:
+    """Turn the library's stage timers on (resetting them) or off."""
+    check(_lib.load().dfpt2_profile_enable(1 if on else 0))
+
+
+def profile_read() -> dict:
+    """{stage: (milliseconds, timed launches)} accumulated since profile_enable."""
+    n = len(_lib.STAGES)
+    ms = (ctypes.c_double * n)()
+    cnt = (ctypes.c_int64 * n)()
+    check(_lib.load().dfpt2_profile_read(ms, cnt))
+    return {name: (ms[i], int(cnt[i])) for i, name in enumerate(_lib.STAGES)}

@@ -26,6 +26,7 @@ SOURCES = [
     "eigh.hip",
     "fno.hip",
     "correction.cpp",
+    "prof.cpp",
 ]
 
 HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"

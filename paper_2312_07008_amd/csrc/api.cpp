@@ -171,8 +171,11 @@ int run_pass_fp64(const PassPlan& pl, const dfpt2_opts& o, const double* eps_h, 
   double* Dpart = reinterpret_cast<double*>(ws + pl.off_Dpart);
   const size_t mat = (size_t)pl.n_v * pl.n_v;
 
-  if ((e = launch_build_pairs(mask, pl.n_core, pl.n_h, pairs, d_count, s)) != hipSuccess)
-    return hip_fail(e, "build_pairs");
+  {
+    ProfScope ps(DFPT2_STAGE_REDUCE, s);
+    if ((e = launch_build_pairs(mask, pl.n_core, pl.n_h, pairs, d_count, s)) != hipSuccess)
+      return hip_fail(e, "build_pairs");
+  }
   int count = 0;
   if ((e = hipMemcpyAsync(&count, d_count, sizeof(int), hipMemcpyDeviceToHost, s)) != hipSuccess)
     return hip_fail(e, "count copy");
@@ -212,9 +215,15 @@ int run_pass_fp64(const PassPlan& pl, const dfpt2_opts& o, const double* eps_h, 
   for (int p0 = 0, b = 0; p0 < count; p0 += pl.batch, ++b) {
     const int np = (count - p0 < pl.batch) ? count - p0 : pl.batch;
     pa.pairs = pairs + p0;
-    if ((e = launch_pair_gemm_f64(pa, np, s)) != hipSuccess) return hip_fail(e, "pair kernel");
-    if ((e = launch_pair_reduce(epart, tpart, pl.nTP, np, pe + 2 * (size_t)p0, tn2 + p0, s)) != hipSuccess)
-      return hip_fail(e, "pair reduce");
+    {
+      ProfScope ps(DFPT2_STAGE_PAIR, s);
+      if ((e = launch_pair_gemm_f64(pa, np, s)) != hipSuccess) return hip_fail(e, "pair kernel");
+    }
+    {
+      ProfScope ps(DFPT2_STAGE_REDUCE, s);
+      if ((e = launch_pair_reduce(epart, tpart, pl.nTP, np, pe + 2 * (size_t)p0, tn2 + p0, s)) != hipSuccess)
+        return hip_fail(e, "pair reduce");
+    }
     da.pairs = pairs + p0;
     da.n_pairs = np;
     da.nsplit = pl.nsplit < np ? pl.nsplit : np;
@@ -225,21 +234,28 @@ int run_pass_fp64(const PassPlan& pl, const dfpt2_opts& o, const double* eps_h, 
       if ((e = launch_fill(Dpart, mat * pl.nsplit, 0.0, s)) != hipSuccess) return hip_fail(e, "fill");
       da.accumulate = 1;
     }
-    if ((e = launch_density_f64(da, s)) != hipSuccess) return hip_fail(e, "density kernel");
+    {
+      ProfScope ps(DFPT2_STAGE_DENSITY, s);
+      if ((e = launch_density_f64(da, s)) != hipSuccess) return hip_fail(e, "density kernel");
+    }
   }
-  if (count == 0) {
-    if ((e = launch_fill(D, mat, 0.0, s)) != hipSuccess) return hip_fail(e, "fill");
-  } else {
-    if ((e = launch_density_reduce(Dpart, pl.nsplit, pl.n_v, D, s)) != hipSuccess)
-      return hip_fail(e, "density reduce");
+  {
+    ProfScope ps_tail(DFPT2_STAGE_REDUCE, s);
+    if (count == 0) {
+      if ((e = launch_fill(D, mat, 0.0, s)) != hipSuccess) return hip_fail(e, "fill");
+    } else {
+      if ((e = launch_density_reduce(Dpart, pl.nsplit, pl.n_v, D, s)) != hipSuccess)
+        return hip_fail(e, "density reduce");
+    }
+    if ((e = launch_energy_finalize(pe, tn2, pairs, d_count, pl.n_up, pl.n_h, e_out, pair_energy, pair_tnorm,
+                                    s)) != hipSuccess)
+      return hip_fail(e, "energy finalize");
   }
-  if ((e = launch_energy_finalize(pe, tn2, pairs, d_count, pl.n_up, pl.n_h, e_out, pair_energy, pair_tnorm, s)) !=
-      hipSuccess)
-    return hip_fail(e, "energy finalize");
   double eh[2];
   if ((e = hipMemcpyAsync(eh, e_out, sizeof(eh), hipMemcpyDeviceToHost, s)) != hipSuccess)
     return hip_fail(e, "energy copy");
   if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "stream sync");
+  prof_flush();
   if (!std::isfinite(eh[0]) || !std::isfinite(eh[1])) return fail(DFPT2_ERR_NONFINITE, "PT2 energy is not finite");
   return DFPT2_OK;
 }

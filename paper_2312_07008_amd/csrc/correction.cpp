@@ -89,8 +89,10 @@ int energy_only_pass(int n_core, int n_h, int n_v, int n_aux, double s, const do
                      hipStream_t st) {
   hipError_t e;
   const int nt = (n_v + 63) / 64, nTP = nt * (nt + 1) / 2;
+  ProfScope ps_pairs(DFPT2_STAGE_REDUCE, st);
   if ((e = launch_build_pairs(nullptr, n_core, n_h, pairs, d_count, st)) != hipSuccess)
     return hip_fail(e, "build_pairs");
+  ps_pairs.close();
   const int n_up = n_core * (n_core + 1) / 2;
   PairKernelArgs pa{};
   pa.B = Bv;
@@ -106,8 +108,10 @@ int energy_only_pass(int n_core, int n_h, int n_v, int n_aux, double s, const do
     const int np = (n_up - p0 < 65535) ? n_up - p0 : 65535;
     pa.pairs = pairs + p0;
     pa.epart = epart + (size_t)p0 * nTP;
+    ProfScope ps(DFPT2_STAGE_KEPT_PAIR, st);
     if ((e = launch_pair_gemm_f64(pa, np, st)) != hipSuccess) return hip_fail(e, "pair kernel");
   }
+  ProfScope ps_red(DFPT2_STAGE_REDUCE, st);
   if ((e = launch_pair_reduce(epart, nullptr, nTP, n_up, pe, nullptr, st)) != hipSuccess)
     return hip_fail(e, "pair reduce");
   if ((e = launch_energy_finalize(pe, nullptr, pairs, d_count, n_up, n_h, e_out, nullptr, nullptr, st)) != hipSuccess)
@@ -159,26 +163,33 @@ int pt2_energy_correction(const dfpt2_opts* opts, const double* eps_hole, const 
   const int nv = cp.n_v, nk = cp.nk;
   hipError_t e;
   // F' = V_k^T diag(eps) V_k
+  ProfScope ps_f(DFPT2_STAGE_TRANSFORM, s);
   hipLaunchKernelGGL(scale_rows_kernel, dim3((nk + 255) / 256, nv), dim3(256), 0, s, no_vecs, nv, eps_vir, nv, nk, Y);
   if ((e = gemm_f64(no_vecs, nv, 0, 1, Y, nk, 0, 0, F, nk, 0, nk, nk, nv, 1, 1.0, 0.0, s)) != hipSuccess)
     return hip_fail(e, "gemm F");
   hipLaunchKernelGGL(symmetrize_kernel, dim3((nk + 255) / 256, nk), dim3(256), 0, s, F, nk);
   if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "symmetrize");
+  ps_f.close();
   st = eigh_run(F, nk, et, W, ws + cp.off_eig, cp.eig_bytes, s, 0);
   if (st != DFPT2_OK) return st;
   // U = V_k W ; B~_i = U^T B_i
+  ProfScope ps_u(DFPT2_STAGE_TRANSFORM, s);
   if ((e = gemm_f64(no_vecs, nv, 0, 0, W, nk, 0, 0, U, nk, 0, nv, nk, nk, 1, 1.0, 0.0, s)) != hipSuccess)
     return hip_fail(e, "gemm U");
   if ((e = gemm_f64(U, nk, 0, 1, B, cp.n_aux, (long long)nv * cp.n_aux, 0, Bt, cp.n_aux, (long long)nk * cp.n_aux,
                     nk, cp.n_aux, nv, cp.n_h, 1.0, 0.0, s)) != hipSuccess)
     return hip_fail(e, "gemm Bt");
+  ps_u.close();
   st = energy_only_pass(cp.n_core, cp.n_h, nk, cp.n_aux, opts->s, eps_hole, et, Bt, pairs, d_count, epart, pe, e_kept, s);
   if (st != DFPT2_OK) return st;
+  ProfScope ps_sub(DFPT2_STAGE_REDUCE, s);
   hipLaunchKernelGGL(dd_sub_kernel, dim3(1), dim3(64), 0, s, e_full, e_kept, correction);
   if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "dd_sub");
+  ps_sub.close();
   double h[2];
   if ((e = hipMemcpyAsync(h, e_kept, 16, hipMemcpyDeviceToHost, s)) != hipSuccess) return hip_fail(e, "copy");
   if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "sync");
+  prof_flush();
   if (!std::isfinite(h[0]) || !std::isfinite(h[1])) return fail(DFPT2_ERR_NONFINITE, "kept-space energy is not finite");
   return DFPT2_OK;
 }

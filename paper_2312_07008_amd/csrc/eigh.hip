@@ -472,6 +472,7 @@ int eigh_run(const double* A_in, int n, double* w_out, double* Z_out, char* ws, 
   int* status = rank + n;
   double* tnorm = (double*)take(64);
   hipError_t err;
+  ProfScope prof_all(DFPT2_STAGE_EIGH, st);
   if ((err = hipMemcpyAsync(A, A_in, nn * 8, hipMemcpyDeviceToDevice, st)) != hipSuccess)
     return hip_fail(err, "eigh copy");
   hipLaunchKernelGGL(zero_int, dim3(1), dim3(64), 0, st, status, 1);
@@ -507,10 +508,12 @@ int eigh_run(const double* A_in, int n, double* w_out, double* Z_out, char* ws, 
   hipLaunchKernelGGL(eig_rank, dim3((n + 255) / 256), dim3(256), 0, st, n, lam, rank);
   hipLaunchKernelGGL(eig_permute, dim3(n), dim3(256), 0, st, n, lam, rank, X, w_out, Z_out, descending);
   if ((err = hipGetLastError()) != hipSuccess) return hip_fail(err, "eigh launch");
+  prof_all.close();
   int hs = 0;
   if ((err = hipMemcpyAsync(&hs, status, sizeof(int), hipMemcpyDeviceToHost, st)) != hipSuccess)
     return hip_fail(err, "eigh status copy");
   if ((err = hipStreamSynchronize(st)) != hipSuccess) return hip_fail(err, "eigh sync");
+  prof_flush();
   if (hs != 0) return fail(DFPT2_ERR_NOT_CONVERGED, "inverse iteration produced a zero or non-finite vector");
   return DFPT2_OK;
 }

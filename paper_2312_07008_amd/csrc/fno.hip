@@ -187,10 +187,12 @@ int fno_truncate(const double* D_vv, int64_t n_vir, double p_o, double degen_rel
   int64_t* d_kept = reinterpret_cast<int64_t*>(tail);
   double* d_marg = reinterpret_cast<double*>(tail + 64);
   int* d_flag = reinterpret_cast<int*>(tail + 128);
+  ProfScope ps_thr(DFPT2_STAGE_REDUCE, st);
   hipLaunchKernelGGL(po_threshold_kernel, dim3(1), dim3(64), 0, st, occ, (int)n_vir, p_o, degen_rel_tol, d_kept,
                      d_marg, d_flag);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "threshold kernel");
+  ps_thr.close();
   struct {
     int64_t kept;
     double marg[2];
@@ -200,6 +202,7 @@ int fno_truncate(const double* D_vv, int64_t n_vir, double p_o, double degen_rel
   if ((e = hipMemcpyAsync(h.marg, d_marg, 16, hipMemcpyDeviceToHost, st)) != hipSuccess) return hip_fail(e, "copy");
   if ((e = hipMemcpyAsync(&h.flag, d_flag, 4, hipMemcpyDeviceToHost, st)) != hipSuccess) return hip_fail(e, "copy");
   if ((e = hipStreamSynchronize(st)) != hipSuccess) return hip_fail(e, "sync");
+  prof_flush();
   if (h.flag) return fail(DFPT2_ERR_NONFINITE, "non-finite occupation number");
   *n_kept = h.kept;
   if (margins) {

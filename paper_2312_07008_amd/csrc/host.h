@@ -32,6 +32,20 @@ int run_pass_fp64(const PassPlan& pl, const dfpt2_opts& o, const double* eps_h, 
                   const double* B, const uint8_t* mask, double* D, double* e_out, double* pair_energy,
                   float* pair_tnorm, char* ws, hipStream_t s);
 
+// Stage timer scope (see dfpt2_profile_enable); no-op unless profiling is on.
+class ProfScope {
+ public:
+  ProfScope(int stage, hipStream_t s);
+  ~ProfScope() { close(); }
+  void close();  // records the end event now; later calls and the destructor do nothing
+ private:
+  int stage_;
+  hipStream_t s_;
+  hipEvent_t a_;
+};
+void prof_flush();
+bool prof_on();
+
 hipError_t gemm_f64(const double* A, int lda, long long sA, int transA, const double* B, int ldb, long long sB,
                     int transB, double* C, int ldc, long long sC, int M, int N, int K, int batch, double alpha,
                     double beta, hipStream_t st);

@@ -29,7 +29,8 @@ constexpr int KC = 16;        // aux chunk per pipeline stage
 constexpr int LDK = KC + 1;   // padded LDS row (doubles)
 }
 
-template <bool VEC>
+// STORE = false: energy-only variant (kept-space pass) that writes no amplitudes.
+template <bool VEC, bool STORE>
 __global__ __launch_bounds__(256, 2) void pair_gemm_f64_kernel(PairKernelArgs a) {
   __shared__ double lds[2][4][TM][LDK];
   __shared__ double red[2][4];
@@ -149,8 +150,8 @@ __global__ __launch_bounds__(256, 2) void pair_gemm_f64_kernel(PairKernelArgs a)
   const double s = a.s;
   const bool offdiag = (I < J);
   const double blk_w = (offdiag ? 2.0 : 1.0) * (same ? 0.5 : 1.0) * a.e_weight;
-  double* Tp = a.T ? a.T + (size_t)p * n_v * n_v : nullptr;
-  double* Vp = a.Vr ? a.Vr + (size_t)p * n_v * n_v : nullptr;
+  double* Tp = (STORE && a.T) ? a.T + (size_t)p * n_v * n_v : nullptr;
+  double* Vp = (STORE && a.Vr) ? a.Vr + (size_t)p * n_v * n_v : nullptr;
   double esum = 0.0, tsum = 0.0;
 #pragma unroll
   for (int bi = 0; bi < 2; ++bi) {
@@ -172,11 +173,11 @@ __global__ __launch_bounds__(256, 2) void pair_gemm_f64_kernel(PairKernelArgs a)
         const double tp_ = vp * g1, tq_ = vq * g1;
         esum += (1.0 + x) * g1 * (2.0 * vp * vp + 2.0 * vq * vq - 2.0 * vp * vq);
         tsum += tp_ * tp_ + (offdiag ? tq_ * tq_ : 0.0);
-        if (Tp) {
+        if (STORE && Tp) {
           Tp[(size_t)ga * n_v + gb] = tp_;
           if (offdiag) Tp[(size_t)gb * n_v + ga] = tq_;
         }
-        if (Vp) {
+        if (STORE && Vp) {
           Vp[(size_t)ga * n_v + gb] = vp * (1.0 + x);
           if (offdiag) Vp[(size_t)gb * n_v + ga] = vq * (1.0 + x);
         }
@@ -200,10 +201,16 @@ __global__ __launch_bounds__(256, 2) void pair_gemm_f64_kernel(PairKernelArgs a)
 hipError_t launch_pair_gemm_f64(const PairKernelArgs& a, int n_pairs, hipStream_t st) {
   if (n_pairs <= 0) return hipSuccess;
   dim3 grid(a.nTP, n_pairs), block(256);
-  if ((a.n_aux % 2) == 0)
-    hipLaunchKernelGGL(pair_gemm_f64_kernel<true>, grid, block, 0, st, a);
+  const bool vec = (a.n_aux % 2) == 0;
+  const bool store = (a.T != nullptr) || (a.Vr != nullptr);
+  if (vec && store)
+    hipLaunchKernelGGL((pair_gemm_f64_kernel<true, true>), grid, block, 0, st, a);
+  else if (vec)
+    hipLaunchKernelGGL((pair_gemm_f64_kernel<true, false>), grid, block, 0, st, a);
+  else if (store)
+    hipLaunchKernelGGL((pair_gemm_f64_kernel<false, true>), grid, block, 0, st, a);
   else
-    hipLaunchKernelGGL(pair_gemm_f64_kernel<false>, grid, block, 0, st, a);
+    hipLaunchKernelGGL((pair_gemm_f64_kernel<false, false>), grid, block, 0, st, a);
   return hipGetLastError();
 }
 
