@@ -26,6 +26,8 @@ SOURCES = [
     "eigh.hip",
     "fno.hip",
     "correction.cpp",
+    "split.hip",
+    "pair_bf16.hip",
     "prof.cpp",
 ]
 

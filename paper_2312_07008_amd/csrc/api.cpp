@@ -79,6 +79,12 @@ int plan_pass(const dfpt2_opts* o, PassPlan* pl) {
   if (nsplit < 1) nsplit = 1;
   p.nsplit = nsplit;
   p.w_density = (o->density_convention == 0) ? 2.0 : 1.0;
+  p.precision = o->precision;
+  p.ns1 = o->slices_gemm1 ? o->slices_gemm1 : default_slices_gemm1(o->precision);
+  p.n_v_pad = (p.n_v + 63) / 64 * 64;
+  p.n_aux_pad = (p.n_aux + 15) / 16 * 16;
+  if (p.precision == DFPT2_BF16_SLICED && (p.ns1 < 2 || p.ns1 > 5))
+    return fail(DFPT2_ERR_INVALID_ARG, "slices_gemm1 must lie in [2, 5] for BF16 slicing");
 
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -94,6 +100,10 @@ int plan_pass(const dfpt2_opts* o, PassPlan* pl) {
   p.off_pe = take(sizeof(double) * 2 * (size_t)(p.n_up > 0 ? p.n_up : 1));
   p.off_tn2 = take(sizeof(double) * (size_t)(p.n_up > 0 ? p.n_up : 1));
   p.off_Dpart = take(sizeof(double) * mat * p.nsplit);
+  p.off_Bs = take(p.precision == DFPT2_BF16_SLICED
+                      ? (size_t)p.ns1 * p.n_h * p.n_v_pad * p.n_aux_pad * sizeof(__bf16)
+                      : 0);
+  p.off_norm2 = take(p.precision == DFPT2_BF16_SLICED ? sizeof(double) * (size_t)p.n_h * p.n_v : 0);
   p.ws_bytes = off;
   return DFPT2_OK;
 }
@@ -146,10 +156,10 @@ int dfpt2_build_vv_density(const dfpt2_opts* opts, const double* eps_hole, const
   if (ws_bytes < pl.ws_bytes)
     return fail(DFPT2_ERR_WORKSPACE, "workspace has %zu bytes, %zu needed", ws_bytes, pl.ws_bytes);
   if (pl.n_act > 0) return fail(DFPT2_ERR_UNSUPPORTED, "active holes are not supported by this build");
-  if (opts->precision != DFPT2_FP64)
+  if (opts->precision == DFPT2_FP8_SLICED)
     return fail(DFPT2_ERR_UNSUPPORTED, "precision %d is not supported by this build", opts->precision);
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  return run_pass_fp64(pl, *opts, eps_hole, eps_vir, B, pair_mask, D_vv, e_pt2, pair_energy, pair_tnorm,
+  return run_pass(pl, *opts, eps_hole, eps_vir, B, pair_mask, D_vv, e_pt2, pair_energy, pair_tnorm,
                        static_cast<char*>(workspace), s);
 }
 
@@ -157,9 +167,33 @@ int dfpt2_build_vv_density(const dfpt2_opts* opts, const double* eps_hole, const
 
 namespace dfpt2 {
 
-int run_pass_fp64(const PassPlan& pl, const dfpt2_opts& o, const double* eps_h, const double* eps_v,
-                  const double* B, const uint8_t* mask, double* D, double* e_out, double* pair_energy,
-                  float* pair_tnorm, char* ws, hipStream_t s) {
+int default_slices_gemm1(int precision) { return precision == DFPT2_BF16_SLICED ? 4 : 1; }
+
+hipError_t launch_pair(const PairLaunch& L, const PairKernelArgs& a, int n_pairs, hipStream_t st) {
+  if (L.precision == DFPT2_FP64) return launch_pair_gemm_f64(a, n_pairs, st);
+  PairBf16Args b{};
+  b.Bs = L.Bs;
+  b.slice_stride = L.slice_stride;
+  b.norm2 = L.norm2;
+  b.eps_h = a.eps_h;
+  b.eps_v = a.eps_v;
+  b.pairs = a.pairs;
+  b.T = a.T;
+  b.epart = a.epart;
+  b.tpart = a.tpart;
+  b.n_v = a.n_v;
+  b.n_v_pad = L.n_v_pad;
+  b.n_aux_pad = L.n_aux_pad;
+  b.nt = a.nt;
+  b.nTP = a.nTP;
+  b.s = a.s;
+  b.e_weight = a.e_weight;
+  return launch_pair_gemm_bf16(b, L.ns, n_pairs, st);
+}
+
+int run_pass(const PassPlan& pl, const dfpt2_opts& o, const double* eps_h, const double* eps_v,
+             const double* B, const uint8_t* mask, double* D, double* e_out, double* pair_energy,
+             float* pair_tnorm, char* ws, hipStream_t s) {
   hipError_t e;
   int2* pairs = reinterpret_cast<int2*>(ws + pl.off_pairs);
   int* d_count = reinterpret_cast<int*>(ws + pl.off_count);
@@ -171,6 +205,18 @@ int run_pass_fp64(const PassPlan& pl, const dfpt2_opts& o, const double* eps_h, 
   double* Dpart = reinterpret_cast<double*>(ws + pl.off_Dpart);
   const size_t mat = (size_t)pl.n_v * pl.n_v;
 
+  PairLaunch L{pl.precision, pl.ns1, B, nullptr, 0, pl.n_v_pad, pl.n_aux_pad, nullptr};
+  if (pl.precision == DFPT2_BF16_SLICED) {
+    ProfScope ps(DFPT2_STAGE_SPLIT, s);
+    __bf16* Bs = reinterpret_cast<__bf16*>(ws + pl.off_Bs);
+    L.Bs = Bs;
+    L.slice_stride = (long long)pl.n_h * pl.n_v_pad * pl.n_aux_pad;
+    double* nrm = reinterpret_cast<double*>(ws + pl.off_norm2);
+    L.norm2 = nrm;
+    if ((e = launch_split_rows_bf16(B, pl.n_aux, pl.n_h, pl.n_v, pl.n_v_pad, pl.n_aux, pl.n_aux_pad, pl.ns1, Bs,
+                                    nrm, s)) != hipSuccess)
+      return hip_fail(e, "split");
+  }
   {
     ProfScope ps(DFPT2_STAGE_REDUCE, s);
     if ((e = launch_build_pairs(mask, pl.n_core, pl.n_h, pairs, d_count, s)) != hipSuccess)
@@ -217,7 +263,7 @@ int run_pass_fp64(const PassPlan& pl, const dfpt2_opts& o, const double* eps_h, 
     pa.pairs = pairs + p0;
     {
       ProfScope ps(DFPT2_STAGE_PAIR, s);
-      if ((e = launch_pair_gemm_f64(pa, np, s)) != hipSuccess) return hip_fail(e, "pair kernel");
+      if ((e = launch_pair(L, pa, np, s)) != hipSuccess) return hip_fail(e, "pair kernel");
     }
     {
       ProfScope ps(DFPT2_STAGE_REDUCE, s);

@@ -15,7 +15,9 @@ namespace {
 
 struct CorrPlan {
   int n_h, n_core, n_v, n_aux, nk, nt, nTP, n_up;
+  int precision, ns1, nk_pad, n_aux_pad;
   size_t off_Y, off_F, off_et, off_W, off_U, off_Bt, off_pairs, off_count, off_epart, off_pe, off_tmp, off_eig;
+  size_t off_Bs, off_norm2;
   size_t eig_bytes, total;
 };
 
@@ -33,6 +35,10 @@ int plan_corr(const dfpt2_opts* o, int64_t n_kept, CorrPlan* cp) {
   c.nt = (c.nk + 63) / 64;
   c.nTP = c.nt * (c.nt + 1) / 2;
   c.n_up = pl.n_up;
+  c.precision = pl.precision;
+  c.ns1 = pl.ns1;
+  c.nk_pad = (c.nk + 63) / 64 * 64;
+  c.n_aux_pad = pl.n_aux_pad;
   const size_t nk = c.nk, nv = c.n_v;
   size_t off = 0;
   auto take = [&](size_t b) {
@@ -53,6 +59,10 @@ int plan_corr(const dfpt2_opts* o, int64_t n_kept, CorrPlan* cp) {
   c.off_tmp = take(64);
   c.eig_bytes = eigh_workspace_bytes(c.nk);
   c.off_eig = take(c.eig_bytes);
+  c.off_Bs = take(c.precision == DFPT2_BF16_SLICED
+                      ? (size_t)c.ns1 * c.n_h * c.nk_pad * c.n_aux_pad * sizeof(__bf16)
+                      : 0);
+  c.off_norm2 = take(c.precision == DFPT2_BF16_SLICED ? sizeof(double) * (size_t)c.n_h * c.nk : 0);
   c.total = off;
   return DFPT2_OK;
 }
@@ -85,8 +95,8 @@ __global__ void dd_sub_kernel(const double* a, const double* b, double* out) {
 
 // Energy of the pass in an arbitrary virtual basis (eps_v, Bv with n_v virtuals); closed shell.
 int energy_only_pass(int n_core, int n_h, int n_v, int n_aux, double s, const double* eps_h, const double* eps_v,
-                     const double* Bv, int2* pairs, int* d_count, double* epart, double* pe, double* e_out,
-                     hipStream_t st) {
+                     const double* Bv, const PairLaunch& L, int2* pairs, int* d_count, double* epart, double* pe,
+                     double* e_out, hipStream_t st) {
   hipError_t e;
   const int nt = (n_v + 63) / 64, nTP = nt * (nt + 1) / 2;
   ProfScope ps_pairs(DFPT2_STAGE_REDUCE, st);
@@ -109,7 +119,7 @@ int energy_only_pass(int n_core, int n_h, int n_v, int n_aux, double s, const do
     pa.pairs = pairs + p0;
     pa.epart = epart + (size_t)p0 * nTP;
     ProfScope ps(DFPT2_STAGE_KEPT_PAIR, st);
-    if ((e = launch_pair_gemm_f64(pa, np, st)) != hipSuccess) return hip_fail(e, "pair kernel");
+    if ((e = launch_pair(L, pa, np, st)) != hipSuccess) return hip_fail(e, "pair kernel");
   }
   ProfScope ps_red(DFPT2_STAGE_REDUCE, st);
   if ((e = launch_pair_reduce(epart, nullptr, nTP, n_up, pe, nullptr, st)) != hipSuccess)
@@ -180,7 +190,20 @@ int pt2_energy_correction(const dfpt2_opts* opts, const double* eps_hole, const 
                     nk, cp.n_aux, nv, cp.n_h, 1.0, 0.0, s)) != hipSuccess)
     return hip_fail(e, "gemm Bt");
   ps_u.close();
-  st = energy_only_pass(cp.n_core, cp.n_h, nk, cp.n_aux, opts->s, eps_hole, et, Bt, pairs, d_count, epart, pe, e_kept, s);
+  PairLaunch L{cp.precision, cp.ns1, Bt, nullptr, 0, cp.nk_pad, cp.n_aux_pad, nullptr};
+  if (cp.precision == DFPT2_BF16_SLICED) {
+    ProfScope ps(DFPT2_STAGE_SPLIT, s);
+    __bf16* Bs = (__bf16*)(ws + cp.off_Bs);
+    L.Bs = Bs;
+    L.slice_stride = (long long)cp.n_h * cp.nk_pad * cp.n_aux_pad;
+    double* nrm = (double*)(ws + cp.off_norm2);
+    L.norm2 = nrm;
+    if ((e = launch_split_rows_bf16(Bt, cp.n_aux, cp.n_h, nk, cp.nk_pad, cp.n_aux, cp.n_aux_pad, cp.ns1, Bs, nrm,
+                                    s)) != hipSuccess)
+      return hip_fail(e, "split");
+  }
+  st = energy_only_pass(cp.n_core, cp.n_h, nk, cp.n_aux, opts->s, eps_hole, et, Bt, L, pairs, d_count, epart, pe,
+                        e_kept, s);
   if (st != DFPT2_OK) return st;
   ProfScope ps_sub(DFPT2_STAGE_REDUCE, s);
   hipLaunchKernelGGL(dd_sub_kernel, dim3(1), dim3(64), 0, s, e_full, e_kept, correction);

@@ -7,6 +7,7 @@
 #include <string>
 
 #include "../../include/dfpt2.h"
+#include "kernels.h"
 
 namespace dfpt2 {
 
@@ -22,15 +23,31 @@ struct PassPlan {
   int batch;        // unordered pairs per batch
   int nsplit;       // density split slices
   double w_density; // density weight of one ordered closed-shell pair
-  size_t off_pairs, off_count, off_T, off_epart, off_tpart, off_pe, off_tn2, off_Dpart;
+  int precision;    // dfpt2_precision
+  int ns1;          // slices per operand of the pair product (mixed precision)
+  int n_v_pad, n_aux_pad;
+  size_t off_pairs, off_count, off_T, off_epart, off_tpart, off_pe, off_tn2, off_Dpart, off_Bs, off_norm2;
   size_t ws_bytes;
 };
 
 int plan_pass(const dfpt2_opts* o, PassPlan* pl);
 
-int run_pass_fp64(const PassPlan& pl, const dfpt2_opts& o, const double* eps_h, const double* eps_v,
-                  const double* B, const uint8_t* mask, double* D, double* e_out, double* pair_energy,
-                  float* pair_tnorm, char* ws, hipStream_t s);
+int run_pass(const PassPlan& pl, const dfpt2_opts& o, const double* eps_h, const double* eps_v,
+             const double* B, const uint8_t* mask, double* D, double* e_out, double* pair_energy,
+             float* pair_tnorm, char* ws, hipStream_t s);
+
+// Pair-kernel launcher shared by the pass and the kept-space energy: FP64, or
+// split BF16 from the slices in `Bs` (prepared by the caller).
+struct PairLaunch {
+  int precision, ns;
+  const double* B;
+  const __bf16* Bs;
+  long long slice_stride;
+  int n_v_pad, n_aux_pad;
+  const double* norm2;
+};
+hipError_t launch_pair(const PairLaunch& L, const PairKernelArgs& a, int n_pairs, hipStream_t st);
+int default_slices_gemm1(int precision);
 
 // Stage timer scope (see dfpt2_profile_enable); no-op unless profiling is on.
 class ProfScope {

@@ -20,6 +20,26 @@ struct PairKernelArgs {
 };
 hipError_t launch_pair_gemm_f64(const PairKernelArgs& a, int n_pairs, hipStream_t st);
 
+// -------------------------------------------------------- split-BF16 pair kernel
+struct PairBf16Args {
+  const __bf16* Bs;     // [n_h][n_v_pad][n_aux_pad/16][ns][16] BF16 slices (split.hip)
+  long long slice_stride;  // unused with the chunk-interleaved layout
+  const double* norm2;  // [n_h][n_v] ||B_ia||^2 in FP64: exact diagonal of V^{ii}
+  const double* eps_h;
+  const double* eps_v;
+  const int2* pairs;
+  double* T;            // [n_pairs][n_v][n_v] FP64 amplitudes out, or null
+  double* epart;
+  double* tpart;
+  int n_v, n_v_pad, n_aux_pad, nt, nTP;
+  double s;
+  double e_weight;
+};
+hipError_t launch_pair_gemm_bf16(const PairBf16Args& a, int ns, int n_pairs, hipStream_t st);
+// FP64 rows -> BF16 slices, see split.hip
+hipError_t launch_split_rows_bf16(const double* X, long long ldx, int nb, int rows, int rows_pad, int ncols,
+                                  int ncols_pad, int ns, __bf16* out, double* norm2, hipStream_t st);
+
 // ------------------------------------------------------------- density kernel
 struct DensityKernelArgs {
   const double* T;      // [n_pairs][n_v][n_v] full amplitude matrices of unordered pairs
