@@ -28,6 +28,7 @@ SOURCES = [
     "correction.cpp",
     "split.hip",
     "pair_bf16.hip",
+    "active.hip",
     "prof.cpp",
 ]
 

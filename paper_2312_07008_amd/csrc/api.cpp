@@ -9,6 +9,7 @@
 #include <string>
 
 #include "../../include/dfpt2.h"
+#include "eigh.h"
 #include "host.h"
 #include "kernels.h"
 
@@ -33,7 +34,7 @@ int hip_fail(hipError_t e, const char* what) {
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 // ----------------------------------------------------------- pass planning
-int plan_pass(const dfpt2_opts* o, PassPlan* pl) {
+int plan_pass(const dfpt2_opts* o, PassPlan* pl, bool energy_only) {
   if (!o) return fail(DFPT2_ERR_INVALID_ARG, "opts is null");
   if (o->n_core < 0 || o->n_act < 0 || o->n_vir <= 0 || o->n_aux <= 0)
     return fail(DFPT2_ERR_INVALID_ARG, "sizes must satisfy n_core >= 0, n_act >= 0, n_vir > 0, n_aux > 0");
@@ -63,6 +64,7 @@ int plan_pass(const dfpt2_opts* o, PassPlan* pl) {
   p.n_up = p.n_core * (p.n_core + 1) / 2;
   const size_t mat = (size_t)p.n_v * p.n_v;
   int64_t batch = o->pair_batch;
+  if (energy_only) batch = 65535;
   if (batch == 0) {
     const double cap_bytes = 8.0e9;
     batch = (int64_t)(cap_bytes / (double)(mat * sizeof(double)));
@@ -79,6 +81,7 @@ int plan_pass(const dfpt2_opts* o, PassPlan* pl) {
   if (nsplit < 1) nsplit = 1;
   p.nsplit = nsplit;
   p.w_density = (o->density_convention == 0) ? 2.0 : 1.0;
+  p.energy_only = energy_only;
   p.precision = o->precision;
   p.ns1 = o->slices_gemm1 ? o->slices_gemm1 : default_slices_gemm1(o->precision);
   p.n_v_pad = (p.n_v + 63) / 64 * 64;
@@ -94,16 +97,48 @@ int plan_pass(const dfpt2_opts* o, PassPlan* pl) {
   };
   p.off_pairs = take(sizeof(int2) * (size_t)(p.n_up > 0 ? p.n_up : 1));
   p.off_count = take(sizeof(int) * 4);
-  p.off_T = take(sizeof(double) * mat * p.batch);
+  p.off_T = take(energy_only ? 0 : sizeof(double) * mat * p.batch);
   p.off_epart = take(sizeof(double) * (size_t)p.batch * p.nTP);
   p.off_tpart = take(sizeof(double) * (size_t)p.batch * p.nTP);
   p.off_pe = take(sizeof(double) * 2 * (size_t)(p.n_up > 0 ? p.n_up : 1));
   p.off_tn2 = take(sizeof(double) * (size_t)(p.n_up > 0 ? p.n_up : 1));
-  p.off_Dpart = take(sizeof(double) * mat * p.nsplit);
+  p.off_Dpart = take(energy_only ? 0 : sizeof(double) * mat * p.nsplit);
   p.off_Bs = take(p.precision == DFPT2_BF16_SLICED
                       ? (size_t)p.ns1 * p.n_h * p.n_v_pad * p.n_aux_pad * sizeof(__bf16)
                       : 0);
   p.off_norm2 = take(p.precision == DFPT2_BF16_SLICED ? sizeof(double) * (size_t)p.n_h * p.n_v : 0);
+  // active holes: stacked amplitude/integral matrices before and after the rotation
+  p.n_ca = p.n_core * p.n_act;
+  p.n_aa_un = p.n_act * (p.n_act + 1) / 2;
+  if (p.n_act > 0) {
+    const double budget = 16.0e9;
+    int cap = (int)(budget / (4.0 * (double)mat * sizeof(double)));
+    int cpb = cap / p.n_act;
+    if (cpb < 1) cpb = 1;
+    if (cpb > p.n_core) cpb = p.n_core > 0 ? p.n_core : 1;
+    p.cpb = cpb;
+    p.act_cap = p.n_act * p.n_act > p.n_act * cpb ? p.n_act * p.n_act : p.n_act * cpb;
+    const size_t ac = (size_t)p.act_cap;
+    p.off_act_T = take(sizeof(double) * mat * ac);
+    p.off_act_V = take(sizeof(double) * mat * ac);
+    p.off_act_Tr = take(sizeof(double) * mat * ac);
+    p.off_act_Vr = take(sizeof(double) * mat * ac);
+    p.off_act_pairs = take(sizeof(int2) * ac);
+    p.off_act_slots = take(sizeof(int) * ac);
+    p.off_act_pairs2 = take(sizeof(int2) * ac);
+    p.off_act_slots2 = take(sizeof(int) * ac);
+    p.off_act_wd = take(sizeof(double) * ac);
+    p.off_act_we = take(sizeof(double) * ac);
+    p.off_act_tpart = take(sizeof(double) * ac * p.nTP);
+    p.off_act_tn2 = take(sizeof(double) * ac);
+    p.off_act_epart = take(sizeof(double) * ac * (size_t)p.nt * p.nt);
+    p.off_act_pe = take(sizeof(double) * 2 * (size_t)(p.n_ca + p.n_aa_un));
+    p.off_act_occ = take(sizeof(double) * p.n_act);
+    p.off_act_U = take(sizeof(double) * p.n_act * p.n_act);
+    p.off_act_W = take(sizeof(double) * (size_t)p.n_act * p.n_act * p.n_act * p.n_act);
+    p.act_eig_bytes = eigh_workspace_bytes(p.n_act);
+    p.off_act_eig = take(p.act_eig_bytes);
+  }
   p.ws_bytes = off;
   return DFPT2_OK;
 }
@@ -155,12 +190,11 @@ int dfpt2_build_vv_density(const dfpt2_opts* opts, const double* eps_hole, const
   if (!workspace && pl.ws_bytes) return fail(DFPT2_ERR_INVALID_ARG, "workspace is null");
   if (ws_bytes < pl.ws_bytes)
     return fail(DFPT2_ERR_WORKSPACE, "workspace has %zu bytes, %zu needed", ws_bytes, pl.ws_bytes);
-  if (pl.n_act > 0) return fail(DFPT2_ERR_UNSUPPORTED, "active holes are not supported by this build");
   if (opts->precision == DFPT2_FP8_SLICED)
     return fail(DFPT2_ERR_UNSUPPORTED, "precision %d is not supported by this build", opts->precision);
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  return run_pass(pl, *opts, eps_hole, eps_vir, B, pair_mask, D_vv, e_pt2, pair_energy, pair_tnorm,
-                       static_cast<char*>(workspace), s);
+  return run_pass(pl, *opts, eps_hole, eps_vir, gamma_act, B, pair_mask, D_vv, e_pt2, pair_energy, pair_tnorm,
+                  static_cast<char*>(workspace), s);
 }
 
 }  // extern "C"
@@ -179,6 +213,7 @@ hipError_t launch_pair(const PairLaunch& L, const PairKernelArgs& a, int n_pairs
   b.eps_v = a.eps_v;
   b.pairs = a.pairs;
   b.T = a.T;
+  b.Vr = a.Vr;
   b.epart = a.epart;
   b.tpart = a.tpart;
   b.n_v = a.n_v;
@@ -191,9 +226,137 @@ hipError_t launch_pair(const PairLaunch& L, const PairKernelArgs& a, int n_pairs
   return launch_pair_gemm_bf16(b, L.ns, n_pairs, st);
 }
 
+// Active blocks of the pass (row a6): core-active pairs in batches of cores, then
+// the active-active block; amplitudes and renormalized integrals are rotated to
+// the natural basis of Gamma_act and fed to the density kernel with weights.
+static int run_active_blocks(const PassPlan& pl, const dfpt2_opts& o, const double* eps_h, const double* eps_v,
+                             const double* gamma_act, const PairLaunch& L, double* Dpart, double* pair_energy,
+                             float* pair_tnorm, char* ws, hipStream_t s) {
+  hipError_t e;
+  const int na = pl.n_act, nv = pl.n_v;
+  const long long mat = (long long)nv * nv;
+  double* Tin = reinterpret_cast<double*>(ws + pl.off_act_T);
+  double* Vin = reinterpret_cast<double*>(ws + pl.off_act_V);
+  double* Tout = reinterpret_cast<double*>(ws + pl.off_act_Tr);
+  double* Vout = reinterpret_cast<double*>(ws + pl.off_act_Vr);
+  int2* pairs = reinterpret_cast<int2*>(ws + pl.off_act_pairs);
+  int* slots = reinterpret_cast<int*>(ws + pl.off_act_slots);
+  int2* pairs2 = reinterpret_cast<int2*>(ws + pl.off_act_pairs2);
+  int* slots2 = reinterpret_cast<int*>(ws + pl.off_act_slots2);
+  double* wd = reinterpret_cast<double*>(ws + pl.off_act_wd);
+  double* we = reinterpret_cast<double*>(ws + pl.off_act_we);
+  double* tpart = reinterpret_cast<double*>(ws + pl.off_act_tpart);
+  double* tn2 = reinterpret_cast<double*>(ws + pl.off_act_tn2);
+  double* epart = reinterpret_cast<double*>(ws + pl.off_act_epart);
+  double* pe_act = reinterpret_cast<double*>(ws + pl.off_act_pe);
+  double* occ = reinterpret_cast<double*>(ws + pl.off_act_occ);
+  double* Ua = reinterpret_cast<double*>(ws + pl.off_act_U);
+  double* Wk = reinterpret_cast<double*>(ws + pl.off_act_W);
+  const double scale_d = pl.w_density / 2.0;
+
+  // natural orbitals of the active density: Gamma_act = U diag(n) U^T
+  int st = eigh_run(gamma_act, na, occ, Ua, ws + pl.off_act_eig, pl.act_eig_bytes, s, 0);
+  if (st != DFPT2_OK) return st;
+  ProfScope prof(DFPT2_STAGE_ACTIVE, s);
+  if ((e = launch_kron_uu(Ua, na, Wk, s)) != hipSuccess) return hip_fail(e, "kron");
+
+  PairKernelArgs pa{};
+  pa.B = L.B;
+  pa.eps_h = eps_h;
+  pa.eps_v = eps_v;
+  pa.n_v = nv;
+  pa.n_aux = pl.n_aux;
+  pa.nt = pl.nt;
+  pa.nTP = pl.nTP;
+  pa.s = o.s;
+  pa.e_weight = 1.0;
+  pa.T = Tin;
+  pa.Vr = Vin;
+  pa.epart = nullptr;
+  pa.tpart = tpart;
+  pa.pairs = pairs;
+
+  DensityKernelArgs da{};
+  da.T = Tout;
+  da.n_v = nv;
+  da.nt = pl.nt;
+  da.nTP = pl.nTP;
+  da.w = 1.0;
+  da.pw = wd;
+  da.Dpart = Dpart;
+  da.accumulate = 1;
+  const int ntile = pl.nt * pl.nt;
+
+  // core-active: T'_{mk} = sum_u U_uk T_{mu}, weight n_k
+  for (int m0 = 0; m0 < pl.n_core; m0 += pl.cpb) {
+    const int nc = (pl.n_core - m0 < pl.cpb) ? pl.n_core - m0 : pl.cpb;
+    const int np = nc * na;
+    if ((e = launch_build_active_pairs(0, m0, nc, pl.n_core, na, pairs, slots, s)) != hipSuccess)
+      return hip_fail(e, "active pairs");
+    if ((e = launch_pair(L, pa, np, s)) != hipSuccess) return hip_fail(e, "pair kernel (core-active)");
+    if ((e = launch_pair_reduce(nullptr, tpart, pl.nTP, np, nullptr, tn2, s)) != hipSuccess)
+      return hip_fail(e, "pair reduce");
+    if ((e = launch_scatter_active_pair_info(pairs, tn2, np, pl.n_h, pair_energy, pair_tnorm, s)) != hipSuccess)
+      return hip_fail(e, "scatter");
+    if ((e = gemm_f64(Ua, na, 0, 1, Tin, (int)mat, mat * na, 0, Tout, (int)mat, mat * na, na, (int)mat, na, nc, 1.0,
+                      0.0, s)) != hipSuccess)
+      return hip_fail(e, "rotate T");
+    if ((e = gemm_f64(Ua, na, 0, 1, Vin, (int)mat, mat * na, 0, Vout, (int)mat, mat * na, na, (int)mat, na, nc, 1.0,
+                      0.0, s)) != hipSuccess)
+      return hip_fail(e, "rotate V");
+    if ((e = launch_active_weights(0, np, pl.n_core, na, pairs, occ, scale_d, wd, we, s)) != hipSuccess)
+      return hip_fail(e, "weights");
+    if ((e = launch_rotated_energy(Tout, Vout, slots, np, nv, epart, s)) != hipSuccess)
+      return hip_fail(e, "rotated energy");
+    if ((e = launch_weighted_pair_reduce(epart, ntile, np, we, pe_act + 2 * (size_t)m0 * na, s)) != hipSuccess)
+      return hip_fail(e, "weighted reduce");
+    if (pl.energy_only) continue;
+    da.pairs = pairs;
+    da.slot = slots;
+    da.n_pairs = np;
+    da.nsplit = pl.nsplit < np ? pl.nsplit : np;
+    if ((e = launch_density_f64(da, s)) != hipSuccess) return hip_fail(e, "density (core-active)");
+  }
+
+  // active-active: all ordered (u, v), rotated with U (x) U, then unordered k <= l
+  {
+    const int np = na * na;
+    if ((e = launch_build_active_pairs(1, 0, 0, pl.n_core, na, pairs, slots, s)) != hipSuccess)
+      return hip_fail(e, "active pairs");
+    if ((e = launch_pair(L, pa, np, s)) != hipSuccess) return hip_fail(e, "pair kernel (active-active)");
+    if ((e = launch_pair_reduce(nullptr, tpart, pl.nTP, np, nullptr, tn2, s)) != hipSuccess)
+      return hip_fail(e, "pair reduce");
+    if ((e = launch_scatter_active_pair_info(pairs, tn2, np, pl.n_h, pair_energy, pair_tnorm, s)) != hipSuccess)
+      return hip_fail(e, "scatter");
+    if ((e = gemm_f64(Wk, np, 0, 1, Tin, (int)mat, 0, 0, Tout, (int)mat, 0, np, (int)mat, np, 1, 1.0, 0.0, s)) !=
+        hipSuccess)
+      return hip_fail(e, "rotate T");
+    if ((e = gemm_f64(Wk, np, 0, 1, Vin, (int)mat, 0, 0, Vout, (int)mat, 0, np, (int)mat, np, 1, 1.0, 0.0, s)) !=
+        hipSuccess)
+      return hip_fail(e, "rotate V");
+    const int nu = pl.n_aa_un;
+    if ((e = launch_build_active_pairs(2, 0, 0, pl.n_core, na, pairs2, slots2, s)) != hipSuccess)
+      return hip_fail(e, "active pairs");
+    if ((e = launch_active_weights(2, nu, pl.n_core, na, pairs2, occ, scale_d, wd, we, s)) != hipSuccess)
+      return hip_fail(e, "weights");
+    if ((e = launch_rotated_energy(Tout, Vout, slots2, nu, nv, epart, s)) != hipSuccess)
+      return hip_fail(e, "rotated energy");
+    if ((e = launch_weighted_pair_reduce(epart, ntile, nu, we, pe_act + 2 * (size_t)pl.n_ca, s)) != hipSuccess)
+      return hip_fail(e, "weighted reduce");
+    if (!pl.energy_only) {
+      da.pairs = pairs2;
+      da.slot = slots2;
+      da.n_pairs = nu;
+      da.nsplit = pl.nsplit < nu ? pl.nsplit : nu;
+      if ((e = launch_density_f64(da, s)) != hipSuccess) return hip_fail(e, "density (active-active)");
+    }
+  }
+  return DFPT2_OK;
+}
+
 int run_pass(const PassPlan& pl, const dfpt2_opts& o, const double* eps_h, const double* eps_v,
-             const double* B, const uint8_t* mask, double* D, double* e_out, double* pair_energy,
-             float* pair_tnorm, char* ws, hipStream_t s) {
+             const double* gamma_act, const double* B, const uint8_t* mask, double* D, double* e_out,
+             double* pair_energy, float* pair_tnorm, char* ws, hipStream_t s) {
   hipError_t e;
   int2* pairs = reinterpret_cast<int2*>(ws + pl.off_pairs);
   int* d_count = reinterpret_cast<int*>(ws + pl.off_count);
@@ -237,6 +400,11 @@ int run_pass(const PassPlan& pl, const dfpt2_opts& o, const double* eps_h, const
       return hip_fail(e, "fill");
   }
 
+  if (!pl.energy_only) {
+    ProfScope ps(DFPT2_STAGE_REDUCE, s);
+    if ((e = launch_fill(Dpart, mat * pl.nsplit, 0.0, s)) != hipSuccess) return hip_fail(e, "fill");
+  }
+  const int stage_pair = pl.energy_only ? DFPT2_STAGE_KEPT_PAIR : DFPT2_STAGE_PAIR;
   PairKernelArgs pa{};
   pa.B = B;
   pa.eps_h = eps_h;
@@ -247,7 +415,7 @@ int run_pass(const PassPlan& pl, const dfpt2_opts& o, const double* eps_h, const
   pa.nTP = pl.nTP;
   pa.s = o.s;
   pa.e_weight = 1.0;  // 1/4 gamma_ii gamma_jj with gamma = 2 for core holes
-  pa.T = T;
+  pa.T = pl.energy_only ? nullptr : T;
   pa.epart = epart;
   pa.tpart = tpart;
 
@@ -262,7 +430,7 @@ int run_pass(const PassPlan& pl, const dfpt2_opts& o, const double* eps_h, const
     const int np = (count - p0 < pl.batch) ? count - p0 : pl.batch;
     pa.pairs = pairs + p0;
     {
-      ProfScope ps(DFPT2_STAGE_PAIR, s);
+      ProfScope ps(stage_pair, s);
       if ((e = launch_pair(L, pa, np, s)) != hipSuccess) return hip_fail(e, "pair kernel");
     }
     {
@@ -270,32 +438,35 @@ int run_pass(const PassPlan& pl, const dfpt2_opts& o, const double* eps_h, const
       if ((e = launch_pair_reduce(epart, tpart, pl.nTP, np, pe + 2 * (size_t)p0, tn2 + p0, s)) != hipSuccess)
         return hip_fail(e, "pair reduce");
     }
+    if (pl.energy_only) continue;
     da.pairs = pairs + p0;
     da.n_pairs = np;
     da.nsplit = pl.nsplit < np ? pl.nsplit : np;
     da.Dpart = Dpart;
-    da.accumulate = (b > 0) ? 1 : 0;
-    // every split slice that exists must be written on the first batch
-    if (b == 0 && da.nsplit < pl.nsplit) {
-      if ((e = launch_fill(Dpart, mat * pl.nsplit, 0.0, s)) != hipSuccess) return hip_fail(e, "fill");
-      da.accumulate = 1;
-    }
+    da.accumulate = 1;
     {
       ProfScope ps(DFPT2_STAGE_DENSITY, s);
       if ((e = launch_density_f64(da, s)) != hipSuccess) return hip_fail(e, "density kernel");
     }
   }
+  if (pl.n_act > 0) {
+    int st = run_active_blocks(pl, o, eps_h, eps_v, gamma_act, L, Dpart, pair_energy, pair_tnorm, ws, s);
+    if (st != DFPT2_OK) return st;
+  }
   {
     ProfScope ps_tail(DFPT2_STAGE_REDUCE, s);
-    if (count == 0) {
-      if ((e = launch_fill(D, mat, 0.0, s)) != hipSuccess) return hip_fail(e, "fill");
-    } else {
+    if (!pl.energy_only) {
       if ((e = launch_density_reduce(Dpart, pl.nsplit, pl.n_v, D, s)) != hipSuccess)
         return hip_fail(e, "density reduce");
     }
     if ((e = launch_energy_finalize(pe, tn2, pairs, d_count, pl.n_up, pl.n_h, e_out, pair_energy, pair_tnorm,
                                     s)) != hipSuccess)
       return hip_fail(e, "energy finalize");
+    if (pl.n_act > 0) {
+      const double* pe_act = reinterpret_cast<const double*>(ws + pl.off_act_pe);
+      if ((e = launch_energy_finalize_active(pe, d_count, pe_act, pl.n_ca + pl.n_aa_un, e_out, s)) != hipSuccess)
+        return hip_fail(e, "energy finalize (active)");
+    }
   }
   double eh[2];
   if ((e = hipMemcpyAsync(eh, e_out, sizeof(eh), hipMemcpyDeviceToHost, s)) != hipSuccess)

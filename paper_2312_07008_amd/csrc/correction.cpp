@@ -14,10 +14,10 @@ namespace dfpt2 {
 namespace {
 
 struct CorrPlan {
-  int n_h, n_core, n_v, n_aux, nk, nt, nTP, n_up;
-  int precision, ns1, nk_pad, n_aux_pad;
-  size_t off_Y, off_F, off_et, off_W, off_U, off_Bt, off_pairs, off_count, off_epart, off_pe, off_tmp, off_eig;
-  size_t off_Bs, off_norm2;
+  int n_h, n_core, n_v, n_aux, nk;
+  PassPlan kp;      // the kept-space pass (energy only)
+  dfpt2_opts ko;    // its options
+  size_t off_Y, off_F, off_et, off_W, off_U, off_Bt, off_eig, off_kp, off_tmp;
   size_t eig_bytes, total;
 };
 
@@ -32,13 +32,11 @@ int plan_corr(const dfpt2_opts* o, int64_t n_kept, CorrPlan* cp) {
   c.n_v = pl.n_v;
   c.n_aux = pl.n_aux;
   c.nk = (int)n_kept;
-  c.nt = (c.nk + 63) / 64;
-  c.nTP = c.nt * (c.nt + 1) / 2;
-  c.n_up = pl.n_up;
-  c.precision = pl.precision;
-  c.ns1 = pl.ns1;
-  c.nk_pad = (c.nk + 63) / 64 * 64;
-  c.n_aux_pad = pl.n_aux_pad;
+  c.ko = *o;
+  c.ko.n_vir = n_kept;
+  c.ko.pair_batch = 0;
+  st = plan_pass(&c.ko, &c.kp, true);
+  if (st != DFPT2_OK) return st;
   const size_t nk = c.nk, nv = c.n_v;
   size_t off = 0;
   auto take = [&](size_t b) {
@@ -52,17 +50,10 @@ int plan_corr(const dfpt2_opts* o, int64_t n_kept, CorrPlan* cp) {
   c.off_W = take(nk * nk * 8);
   c.off_U = take(nv * nk * 8);
   c.off_Bt = take((size_t)c.n_h * nk * c.n_aux * 8);
-  c.off_pairs = take(sizeof(int2) * (size_t)(c.n_up > 0 ? c.n_up : 1));
-  c.off_count = take(16);
-  c.off_epart = take(8 * (size_t)(c.n_up > 0 ? c.n_up : 1) * c.nTP);
-  c.off_pe = take(16 * (size_t)(c.n_up > 0 ? c.n_up : 1));
-  c.off_tmp = take(64);
   c.eig_bytes = eigh_workspace_bytes(c.nk);
   c.off_eig = take(c.eig_bytes);
-  c.off_Bs = take(c.precision == DFPT2_BF16_SLICED
-                      ? (size_t)c.ns1 * c.n_h * c.nk_pad * c.n_aux_pad * sizeof(__bf16)
-                      : 0);
-  c.off_norm2 = take(c.precision == DFPT2_BF16_SLICED ? sizeof(double) * (size_t)c.n_h * c.nk : 0);
+  c.off_kp = take(c.kp.ws_bytes);
+  c.off_tmp = take(64);
   c.total = off;
   return DFPT2_OK;
 }
@@ -93,42 +84,6 @@ __global__ void dd_sub_kernel(const double* a, const double* b, double* out) {
 
 }  // namespace
 
-// Energy of the pass in an arbitrary virtual basis (eps_v, Bv with n_v virtuals); closed shell.
-int energy_only_pass(int n_core, int n_h, int n_v, int n_aux, double s, const double* eps_h, const double* eps_v,
-                     const double* Bv, const PairLaunch& L, int2* pairs, int* d_count, double* epart, double* pe,
-                     double* e_out, hipStream_t st) {
-  hipError_t e;
-  const int nt = (n_v + 63) / 64, nTP = nt * (nt + 1) / 2;
-  ProfScope ps_pairs(DFPT2_STAGE_REDUCE, st);
-  if ((e = launch_build_pairs(nullptr, n_core, n_h, pairs, d_count, st)) != hipSuccess)
-    return hip_fail(e, "build_pairs");
-  ps_pairs.close();
-  const int n_up = n_core * (n_core + 1) / 2;
-  PairKernelArgs pa{};
-  pa.B = Bv;
-  pa.eps_h = eps_h;
-  pa.eps_v = eps_v;
-  pa.n_v = n_v;
-  pa.n_aux = n_aux;
-  pa.nt = nt;
-  pa.nTP = nTP;
-  pa.s = s;
-  pa.e_weight = 1.0;
-  for (int p0 = 0; p0 < n_up; p0 += 65535) {
-    const int np = (n_up - p0 < 65535) ? n_up - p0 : 65535;
-    pa.pairs = pairs + p0;
-    pa.epart = epart + (size_t)p0 * nTP;
-    ProfScope ps(DFPT2_STAGE_KEPT_PAIR, st);
-    if ((e = launch_pair(L, pa, np, st)) != hipSuccess) return hip_fail(e, "pair kernel");
-  }
-  ProfScope ps_red(DFPT2_STAGE_REDUCE, st);
-  if ((e = launch_pair_reduce(epart, nullptr, nTP, n_up, pe, nullptr, st)) != hipSuccess)
-    return hip_fail(e, "pair reduce");
-  if ((e = launch_energy_finalize(pe, nullptr, pairs, d_count, n_up, n_h, e_out, nullptr, nullptr, st)) != hipSuccess)
-    return hip_fail(e, "energy finalize");
-  return DFPT2_OK;
-}
-
 }  // namespace dfpt2
 
 using namespace dfpt2;
@@ -157,7 +112,8 @@ int pt2_energy_correction(const dfpt2_opts* opts, const double* eps_hole, const 
     return fail(DFPT2_ERR_INVALID_ARG, "null pointer argument");
   if (opts->n_act > 0 && !gamma_act) return fail(DFPT2_ERR_INVALID_ARG, "gamma_act is null but n_act > 0");
   if (ws_bytes < cp.total) return fail(DFPT2_ERR_WORKSPACE, "workspace has %zu bytes, %zu needed", ws_bytes, cp.total);
-  if (opts->n_act > 0) return fail(DFPT2_ERR_UNSUPPORTED, "active holes are not supported by this build");
+  if (opts->precision == DFPT2_FP8_SLICED)
+    return fail(DFPT2_ERR_UNSUPPORTED, "precision %d is not supported by this build", opts->precision);
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   char* ws = static_cast<char*>(workspace);
   double* Y = (double*)(ws + cp.off_Y);
@@ -166,10 +122,6 @@ int pt2_energy_correction(const dfpt2_opts* opts, const double* eps_hole, const 
   double* W = (double*)(ws + cp.off_W);
   double* U = (double*)(ws + cp.off_U);
   double* Bt = (double*)(ws + cp.off_Bt);
-  int2* pairs = (int2*)(ws + cp.off_pairs);
-  int* d_count = (int*)(ws + cp.off_count);
-  double* epart = (double*)(ws + cp.off_epart);
-  double* pe = (double*)(ws + cp.off_pe);
   const int nv = cp.n_v, nk = cp.nk;
   hipError_t e;
   // F' = V_k^T diag(eps) V_k
@@ -190,20 +142,9 @@ int pt2_energy_correction(const dfpt2_opts* opts, const double* eps_hole, const 
                     nk, cp.n_aux, nv, cp.n_h, 1.0, 0.0, s)) != hipSuccess)
     return hip_fail(e, "gemm Bt");
   ps_u.close();
-  PairLaunch L{cp.precision, cp.ns1, Bt, nullptr, 0, cp.nk_pad, cp.n_aux_pad, nullptr};
-  if (cp.precision == DFPT2_BF16_SLICED) {
-    ProfScope ps(DFPT2_STAGE_SPLIT, s);
-    __bf16* Bs = (__bf16*)(ws + cp.off_Bs);
-    L.Bs = Bs;
-    L.slice_stride = (long long)cp.n_h * cp.nk_pad * cp.n_aux_pad;
-    double* nrm = (double*)(ws + cp.off_norm2);
-    L.norm2 = nrm;
-    if ((e = launch_split_rows_bf16(Bt, cp.n_aux, cp.n_h, nk, cp.nk_pad, cp.n_aux, cp.n_aux_pad, cp.ns1, Bs, nrm,
-                                    s)) != hipSuccess)
-      return hip_fail(e, "split");
-  }
-  st = energy_only_pass(cp.n_core, cp.n_h, nk, cp.n_aux, opts->s, eps_hole, et, Bt, L, pairs, d_count, epart, pe,
-                        e_kept, s);
+  // kept-space pass (energy only) in the recanonicalized basis (eps~, B~)
+  st = run_pass(cp.kp, cp.ko, eps_hole, et, gamma_act, Bt, nullptr, nullptr, e_kept, nullptr, nullptr,
+                ws + cp.off_kp, s);
   if (st != DFPT2_OK) return st;
   ProfScope ps_sub(DFPT2_STAGE_REDUCE, s);
   hipLaunchKernelGGL(dd_sub_kernel, dim3(1), dim3(64), 0, s, e_full, e_kept, correction);

@@ -49,7 +49,7 @@ __global__ __launch_bounds__(256, 2) void density_f64_kernel(DensityKernelArgs a
   auto load_chunk = [&](int idx) {
     const int p = p0 + idx / ncc;
     const int c0 = (idx % ncc) * KC;
-    const double* Tp = a.T + (size_t)p * n_v * n_v;
+    const double* Tp = a.T + (size_t)(a.slot ? a.slot[p] : p) * n_v * n_v;
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
 #pragma unroll

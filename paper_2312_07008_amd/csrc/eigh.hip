@@ -278,8 +278,12 @@ __global__ void tridiag_inverse_iteration(int n, const double* d, const double* 
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= n) return;
   const int s = blk_start[g], t = blk_end[g];
-  const double nrm = fmax(*tnorm, DBL_MIN);
+  const double nrm = (*tnorm > 0.0) ? *tnorm : 1.0;
   const double grp_tol = 1e-10 * nrm;
+  if (t - s == 1) {  // a 1 x 1 block: the unit vector
+    for (int i = 0; i < n; ++i) X[(size_t)i * n + g] = (i == s) ? 1.0 : 0.0;
+    return;
+  }
   // leader test: previous eigenvalue in the same block is not within grp_tol
   if (g > s && fabs(lam[g] - lam[g - 1]) <= grp_tol) return;
   int g1 = g + 1;
@@ -291,7 +295,6 @@ __global__ void tridiag_inverse_iteration(int n, const double* d, const double* 
     // eigenvalues of a group are spread by a few ulps so that the factors differ
     const double lq = lam[q] + (double)(q - g) * 4.0 * DBL_EPSILON * nrm;
     lu_factor(d, e, s, t, lq, tiny, L, n, g);
-    double nx = 0.0;
     for (int it = 0; it < 4; ++it) {
       lu_solve(s, t, L, n, g, X, q);
       // orthogonalize against earlier vectors of the group (twice for stability)
@@ -302,14 +305,20 @@ __global__ void tridiag_inverse_iteration(int n, const double* d, const double* 
           for (int i = s; i < t; ++i) X[(size_t)i * n + q] -= dp * X[(size_t)i * n + r];
         }
       }
-      nx = 0.0;
-      for (int i = s; i < t; ++i) nx += X[(size_t)i * n + q] * X[(size_t)i * n + q];
-      nx = sqrt(nx);
-      if (!(nx > 0.0) || !isfinite(nx)) {
+      // overflow-safe normalization
+      double mx = 0.0;
+      for (int i = s; i < t; ++i) mx = fmax(mx, fabs(X[(size_t)i * n + q]));
+      if (!(mx > 0.0) || !isfinite(mx)) {
         atomicExch(status, 1);
         return;
       }
-      const double inv = 1.0 / nx;
+      double nx = 0.0;
+      const double inv_mx = 1.0 / mx;
+      for (int i = s; i < t; ++i) {
+        const double y = X[(size_t)i * n + q] * inv_mx;
+        nx += y * y;
+      }
+      const double inv = inv_mx / sqrt(nx);
       for (int i = s; i < t; ++i) X[(size_t)i * n + q] *= inv;
     }
   }

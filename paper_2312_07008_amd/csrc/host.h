@@ -24,17 +24,24 @@ struct PassPlan {
   int nsplit;       // density split slices
   double w_density; // density weight of one ordered closed-shell pair
   int precision;    // dfpt2_precision
+  bool energy_only; // no amplitudes stored, no density (kept-space energy)
   int ns1;          // slices per operand of the pair product (mixed precision)
   int n_v_pad, n_aux_pad;
   size_t off_pairs, off_count, off_T, off_epart, off_tpart, off_pe, off_tn2, off_Dpart, off_Bs, off_norm2;
+  // active holes
+  int n_ca, n_aa_un, cpb, act_cap;
+  size_t off_act_T, off_act_V, off_act_Tr, off_act_Vr, off_act_pairs, off_act_slots, off_act_pairs2,
+      off_act_slots2, off_act_wd, off_act_we, off_act_tpart, off_act_tn2, off_act_epart, off_act_pe, off_act_occ,
+      off_act_U, off_act_W, off_act_eig;
+  size_t act_eig_bytes;
   size_t ws_bytes;
 };
 
-int plan_pass(const dfpt2_opts* o, PassPlan* pl);
+int plan_pass(const dfpt2_opts* o, PassPlan* pl, bool energy_only = false);
 
 int run_pass(const PassPlan& pl, const dfpt2_opts& o, const double* eps_h, const double* eps_v,
-             const double* B, const uint8_t* mask, double* D, double* e_out, double* pair_energy,
-             float* pair_tnorm, char* ws, hipStream_t s);
+             const double* gamma_act, const double* B, const uint8_t* mask, double* D, double* e_out,
+             double* pair_energy, float* pair_tnorm, char* ws, hipStream_t s);
 
 // Pair-kernel launcher shared by the pass and the kept-space energy: FP64, or
 // split BF16 from the slices in `Bs` (prepared by the caller).

@@ -29,6 +29,7 @@ struct PairBf16Args {
   const double* eps_v;
   const int2* pairs;
   double* T;            // [n_pairs][n_v][n_v] FP64 amplitudes out, or null
+  double* Vr;           // [n_pairs][n_v][n_v] renormalized integrals out, or null
   double* epart;
   double* tpart;
   int n_v, n_v_pad, n_aux_pad, nt, nTP;
@@ -45,6 +46,7 @@ struct DensityKernelArgs {
   const double* T;      // [n_pairs][n_v][n_v] full amplitude matrices of unordered pairs
   const double* pw;     // [n_pairs] per-pair weight, or null (then w for every pair)
   const int2* pairs;    // [n_pairs]
+  const int* slot;      // [n_pairs] matrix index of pair p in T, or null (p)
   double* Dpart;        // [nsplit][n_v][n_v]
   int n_v, nt, nTP, n_pairs, nsplit;
   double w;             // weight of one ordered pair (closed shell, spin-summed: 2)
@@ -65,5 +67,20 @@ hipError_t launch_pair_reduce(const double* epart, const double* tpart, int nTP,
 hipError_t launch_energy_finalize(const double* pe, const double* tn2, const int2* pairs,
                                   const int* count, int max_pairs, int n_h, double* e_out,
                                   double* pair_energy, float* pair_tnorm, hipStream_t st);
+
+// ------------------------------------------------------------ active holes
+hipError_t launch_kron_uu(const double* U, int na, double* W, hipStream_t st);
+hipError_t launch_build_active_pairs(int kind, int m0, int ncore, int n_core, int na, int2* pairs, int* slots,
+                                     hipStream_t st);
+hipError_t launch_active_weights(int kind, int n, int n_core, int na, const int2* pairs, const double* occ,
+                                 double scale_d, double* wd, double* we, hipStream_t st);
+hipError_t launch_rotated_energy(const double* T, const double* Vr, const int* slot, int n_pairs, int n_v,
+                                 double* part, hipStream_t st);
+hipError_t launch_weighted_pair_reduce(const double* part, int ntile, int n_pairs, const double* we, double* pe,
+                                       hipStream_t st);
+hipError_t launch_energy_finalize_active(const double* pe, const int* count, const double* pe_act, int n_act_pairs,
+                                         double* e_out, hipStream_t st);
+hipError_t launch_scatter_active_pair_info(const int2* pairs, const double* tn2, int n, int n_h, double* pair_energy,
+                                           float* pair_tnorm, hipStream_t st);
 
 }  // namespace dfpt2

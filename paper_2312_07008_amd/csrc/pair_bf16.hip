@@ -170,6 +170,7 @@ __global__ __launch_bounds__(256, 2) void pair_gemm_bf16_kernel(PairBf16Args a) 
   const bool offdiag = (I < J);
   const double blk_w = (offdiag ? 2.0 : 1.0) * (same ? 0.5 : 1.0) * a.e_weight;
   double* Tp = (STORE && a.T) ? a.T + (size_t)p * n_v * n_v : nullptr;
+  double* Vp = (STORE && a.Vr) ? a.Vr + (size_t)p * n_v * n_v : nullptr;
   double esum = 0.0, tsum = 0.0;
   const int gb = J * TM + wc * 32 + r32;
   const bool vb = gb < n_v;
@@ -190,6 +191,10 @@ __global__ __launch_bounds__(256, 2) void pair_gemm_bf16_kernel(PairBf16Args a) 
       Tp[(size_t)ga * n_v + gb] = tp_;
       if (offdiag) Tp[(size_t)gb * n_v + ga] = tq_;
     }
+    if (STORE && Vp) {
+      Vp[(size_t)ga * n_v + gb] = vp * (1.0 + x);
+      if (offdiag) Vp[(size_t)gb * n_v + ga] = vq * (1.0 + x);
+    }
   }
   esum = wave_sum(esum);
   tsum = wave_sum(tsum);
@@ -208,7 +213,7 @@ __global__ __launch_bounds__(256, 2) void pair_gemm_bf16_kernel(PairBf16Args a) 
 hipError_t launch_pair_gemm_bf16(const PairBf16Args& a, int ns, int n_pairs, hipStream_t st) {
   if (n_pairs <= 0) return hipSuccess;
   dim3 grid(a.nTP, n_pairs), block(256);
-  const bool store = a.T != nullptr;
+  const bool store = a.T != nullptr || a.Vr != nullptr;
 #define DFPT2_LAUNCH(NS_)                                                                          \
   if (store)                                                                                       \
     hipLaunchKernelGGL((pair_gemm_bf16_kernel<NS_, true>), grid, block, 0, st, a);                 \

@@ -89,12 +89,15 @@ def _gpu_eigh(A):
 
 @pytest.mark.parametrize("kind,n", [("random", 1), ("random", 2), ("random", 3), ("random", 97),
                                     ("random", 256), ("identity", 40), ("diag_repeat", 33),
-                                    ("blocks", 60), ("psd_lowrank", 120), ("clustered", 80)])
+                                    ("blocks", 60), ("psd_lowrank", 120), ("clustered", 80), ("zeros", 5),
+                                    ("zeros", 1)])
 def test_eigh_against_lapack(kind, n):
     rng = np.random.default_rng(n)
     if kind == "random":
         X = rng.standard_normal((n, n))
         A = X + X.T
+    elif kind == "zeros":
+        A = np.zeros((n, n))
     elif kind == "identity":
         A = np.eye(n) * 3.0
     elif kind == "diag_repeat":
@@ -114,7 +117,7 @@ def test_eigh_against_lapack(kind, n):
         A = 0.5 * (A + A.T)
     w, Z = _gpu_eigh(A)
     wref = np.linalg.eigvalsh(A)
-    nrm = max(np.abs(wref).max(), 1e-300)
+    nrm = max(np.abs(wref).max(), 1.0 if kind == "zeros" else 1e-300)
     assert np.all(np.diff(w) >= 0)
     assert np.abs(w - wref).max() <= 1e-13 * nrm * max(1.0, np.sqrt(n) / 4)
     assert np.abs(A @ Z - Z * w[None, :]).max() <= 1e-12 * nrm * max(1.0, np.sqrt(n) / 4)
