@@ -165,6 +165,62 @@ int pt2_energy_correction(const dfpt2_opts* opts, const double* eps_hole, const 
                           dfpt2_stream_t stream);
 
 /*
+ * Learned pair screening (not part of the paper's method).  A small network
+ * predicts ||t_ij||_F of every unordered core pair before the pass and the
+ * mask drops pairs predicted below a threshold; the unscreened pass is the
+ * reference it is judged against.  Pair order everywhere: unordered core pairs
+ * i <= j, row-major (n_up = n_core (n_core + 1) / 2 entries).
+ *
+ * Pair quantities (q_iQ = ||B^Q_i.||_2 over virtuals):
+ *   U_ij = sum_Q q_iQ q_jQ >= ||V_ij||_F (rigorous), W_ij = (sum_Q q_iQ^2 q_jQ^2)^(1/2),
+ *   g_ij = max |1 - e^{-s D^2}| / |D| over the pair's denominators D (Eq. A7),
+ *   ||t_ij||_F <= g_ij U_ij.
+ * Features (float, [n_up][5]):
+ *   (e_i, e_j, log(U/W), 0.1 (log W_ij - (log W_ii + log W_jj)/2), 0.1 log(g W)).
+ * log_scale (double, [n_up][2]) = (log(g_ij W_ij), log(g_ij U_ij)).
+ * Network: 5 -> 64 (tanh) -> 64 (tanh) -> 1, FP32 parameters packed as
+ *   [W1 64x5 row-major, b1 64, W2 64x64, b2 64, w3 64, b3 1] (pairscreen_num_params()).
+ * The network output is y = log ||t_ij||_F - log(g_ij W_ij).
+ */
+int pairscreen_num_params(void);
+/* Workspace for pairscreen_features.  bytes: host out. */
+int pairscreen_workspace_size(const dfpt2_opts* opts, size_t* bytes);
+/* eps_hole [n_h], eps_vir [n_vir] ascending, B [n_h][n_vir][n_aux]; feats, log_scale out. */
+int pairscreen_features(const dfpt2_opts* opts, const double* eps_hole, const double* eps_vir,
+                        const double* B, float* feats, double* log_scale,
+                        void* workspace, size_t ws_bytes, dfpt2_stream_t stream);
+/* Forward pass for n samples: W [num_params], feats [n][5] -> pred [n];
+ * act_cache [n][128] out (hidden activations for the backward pass) or NULL. */
+int pairscreen_mlp_forward(const float* W, const float* feats, int64_t n, float* pred, float* act_cache,
+                           dfpt2_stream_t stream);
+/* Gradient of sum_n dpred_n pred_n: dW [num_params] out.  Workspace from
+ * pairscreen_backward_workspace_size(n). */
+int pairscreen_backward_workspace_size(int64_t n, size_t* bytes);
+int pairscreen_mlp_backward(const float* W, const float* feats, const float* act_cache, const float* dpred,
+                            int64_t n, float* dW, void* workspace, size_t ws_bytes, dfpt2_stream_t stream);
+/* One Adam update (bias-corrected, step >= 1) of W with gradient dW and moments m, v. */
+int pairscreen_adam_step(float* W, const float* dW, float* m, float* v, int64_t n_params, float lr, float b1,
+                         float b2, float eps, int64_t step, dfpt2_stream_t stream);
+/* Full-batch training: `steps` iterations of forward, mean squared error against
+ * y [n], backward and Adam (b1 0.9, b2 0.999, eps 1e-8, steps numbered from
+ * step0 + 1); losses [steps] out (device).  Synchronizes the stream. */
+int pairscreen_train_workspace_size(int64_t n, size_t* bytes);
+int pairscreen_train(float* W, float* m, float* v, const float* feats, const float* y, int64_t n, int64_t steps,
+                     int64_t step0, float lr, float* losses, void* workspace, size_t ws_bytes,
+                     dfpt2_stream_t stream);
+/* Training targets y [n_up] = log ||t_ij||_F - log(g_ij W_ij) from the pass's pair_tnorm [n_h][n_h]. */
+int pairscreen_targets(const float* pair_tnorm, const double* log_scale, int64_t n_core, int64_t n_h, float* y,
+                       dfpt2_stream_t stream);
+/* Pair mask [n_h][n_h] for dfpt2_build_vv_density: 1 everywhere except core pairs with
+ *   mode 0 (network): log(g W) + pred + margin < log(threshold)
+ *   mode 1 (rigorous bound): log(g U) < log(threshold).
+ * n_dropped: host out (unordered pairs dropped) or NULL (then no synchronization).
+ * workspace: >= 64 bytes of device scratch. */
+int pairscreen_build_mask(const float* pred, const double* log_scale, int64_t n_core, int64_t n_h,
+                          double threshold, double margin, int mode, uint8_t* mask, int64_t* n_dropped,
+                          void* workspace, size_t ws_bytes, dfpt2_stream_t stream);
+
+/*
  * Stage timers for measurement (not part of the method).  When enabled, every
  * entry point brackets its kernel launches with HIP events on the stream it was
  * given and, at its next stream synchronization, adds the elapsed GPU time to

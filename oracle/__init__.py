@@ -9,6 +9,8 @@ Modules:
              natural orbitals (Eq. 8), truncation (Eqs. 9-10 and the
              near-degeneracy rule of Sec. 2), recanonicalization and the
              additive correction (Eq. 11)
-  screening  (added with the learned pair screen)
+  screening  pair features and rigorous bounds, the FP64 multilayer perceptron,
+             its gradient, mean squared error and Adam, used to check the learned
+             pair screen (which is not part of the paper's method)
 """
-from . import dsrg_pt2  # noqa: F401
+from . import dsrg_pt2, screening  # noqa: F401

@@ -5,6 +5,9 @@ include/dfpt2.h).  This package only loads it and marshals torch device
 tensors into its entry points; there is no CPU fallback.
 """
 from ._lib import (BF16_SLICED, FP8_SLICED, FP64, DfptError, Opts, LIB_PATH, load)  # noqa: F401
+from .api import (pairscreen_adam_step, pairscreen_build_mask, pairscreen_features,  # noqa: F401
+                  pairscreen_mlp_backward, pairscreen_mlp_forward, pairscreen_num_params, pairscreen_targets,
+                  pairscreen_train)
 from .api import (build_vv_density, eigh_sym, fno_truncate, fno_truncate_workspace_size,  # noqa: F401
                   make_opts, profile_enable, profile_read, pt2_correction_workspace_size,
                   pt2_energy_correction, upload_inputs,

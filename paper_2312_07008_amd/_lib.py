@@ -62,6 +62,19 @@ SIGNATURES = {
     "pt2_correction_workspace_size": (_int, [ctypes.POINTER(Opts), _i64, ctypes.POINTER(_sz)]),
     "pt2_energy_correction": (_int, [ctypes.POINTER(Opts), _vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp,
                                      _vp, _sz, _vp]),
+    "pairscreen_num_params": (_int, []),
+    "pairscreen_workspace_size": (_int, [ctypes.POINTER(Opts), ctypes.POINTER(_sz)]),
+    "pairscreen_features": (_int, [ctypes.POINTER(Opts), _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "pairscreen_mlp_forward": (_int, [_vp, _vp, _i64, _vp, _vp, _vp]),
+    "pairscreen_backward_workspace_size": (_int, [_i64, ctypes.POINTER(_sz)]),
+    "pairscreen_mlp_backward": (_int, [_vp, _vp, _vp, _vp, _i64, _vp, _vp, _sz, _vp]),
+    "pairscreen_adam_step": (_int, [_vp, _vp, _vp, _vp, _i64, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                    ctypes.c_float, _i64, _vp]),
+    "pairscreen_train_workspace_size": (_int, [_i64, ctypes.POINTER(_sz)]),
+    "pairscreen_train": (_int, [_vp, _vp, _vp, _vp, _vp, _i64, _i64, _i64, ctypes.c_float, _vp, _vp, _sz, _vp]),
+    "pairscreen_targets": (_int, [_vp, _vp, _i64, _i64, _vp, _vp]),
+    "pairscreen_build_mask": (_int, [_vp, _vp, _i64, _i64, _dbl, _dbl, _int, _vp, ctypes.POINTER(_i64), _vp, _sz,
+                                     _vp]),
     "dfpt2_profile_enable": (_int, [_int]),
     "dfpt2_profile_read": (_int, [ctypes.POINTER(_dbl), ctypes.POINTER(_i64)]),
 }

@@ -17,7 +17,9 @@ from ._lib import Opts, check
 
 __all__ = ["make_opts", "workspace_size", "build_vv_density", "fno_truncate_workspace_size",
            "fno_truncate", "eigh_sym", "pt2_correction_workspace_size", "pt2_energy_correction",
-           "upload_inputs", "profile_enable", "profile_read"]
+           "upload_inputs", "profile_enable", "profile_read", "pairscreen_num_params", "pairscreen_features",
+           "pairscreen_mlp_forward", "pairscreen_mlp_backward", "pairscreen_adam_step", "pairscreen_train",
+           "pairscreen_targets", "pairscreen_build_mask"]
 
 
 def _ptr(t: Optional[torch.Tensor]):
@@ -198,3 +200,106 @@ def profile_read() -> dict:
     cnt = (ctypes.c_int64 * n)()
     check(_lib.load().dfpt2_profile_read(ms, cnt))
     return {name: (ms[i], int(cnt[i])) for i, name in enumerate(_lib.STAGES)}
+
+
+# ----------------------------------------------------------------- pair screening
+
+def pairscreen_num_params() -> int:
+    return int(_lib.load().pairscreen_num_params())
+
+
+def pairscreen_features(opts: Opts, eps_hole, eps_vir, B, *, workspace=None, stream=None):
+    lib = _lib.load()
+    n_h = opts.n_core + opts.n_act
+    n_up = opts.n_core * (opts.n_core + 1) // 2
+    _need(eps_hole, "eps_hole", torch.float64, n_h)
+    _need(eps_vir, "eps_vir", torch.float64, opts.n_vir)
+    _need(B, "B", torch.float64, n_h * opts.n_vir * opts.n_aux)
+    dev = B.device
+    feats = torch.empty((max(n_up, 1), 5), dtype=torch.float32, device=dev)
+    log_scale = torch.empty((max(n_up, 1), 2), dtype=torch.float64, device=dev)
+    n = ctypes.c_size_t(0)
+    check(lib.pairscreen_workspace_size(ctypes.byref(opts), ctypes.byref(n)))
+    ws = _workspace(int(n.value), dev, workspace)
+    check(lib.pairscreen_features(ctypes.byref(opts), _ptr(eps_hole), _ptr(eps_vir), _ptr(B), _ptr(feats),
+                                  _ptr(log_scale), _ptr(ws), ctypes.c_size_t(ws.numel()), _stream(stream)))
+    return feats[:n_up], log_scale[:n_up]
+
+
+def pairscreen_mlp_forward(W, feats, *, want_cache=False, stream=None):
+    lib = _lib.load()
+    n = feats.shape[0]
+    _need(W, "W", torch.float32, pairscreen_num_params())
+    _need(feats, "feats", torch.float32, n * 5)
+    pred = torch.empty(n, dtype=torch.float32, device=feats.device)
+    cache = torch.empty((n, 128), dtype=torch.float32, device=feats.device) if want_cache else None
+    check(lib.pairscreen_mlp_forward(_ptr(W), _ptr(feats), n, _ptr(pred), _ptr(cache), _stream(stream)))
+    return pred, cache
+
+
+def pairscreen_mlp_backward(W, feats, cache, dpred, *, stream=None):
+    lib = _lib.load()
+    n = feats.shape[0]
+    _need(W, "W", torch.float32, pairscreen_num_params())
+    _need(feats, "feats", torch.float32, n * 5)
+    _need(cache, "cache", torch.float32, n * 128)
+    _need(dpred, "dpred", torch.float32, n)
+    dW = torch.empty_like(W)
+    nb = ctypes.c_size_t(0)
+    check(lib.pairscreen_backward_workspace_size(n, ctypes.byref(nb)))
+    ws = _workspace(int(nb.value), feats.device, None)
+    check(lib.pairscreen_mlp_backward(_ptr(W), _ptr(feats), _ptr(cache), _ptr(dpred), n, _ptr(dW), _ptr(ws),
+                                      ctypes.c_size_t(ws.numel()), _stream(stream)))
+    return dW
+
+
+def pairscreen_adam_step(W, dW, m, v, step: int, lr: float, b1=0.9, b2=0.999, eps=1e-8, *, stream=None):
+    lib = _lib.load()
+    for t, nm in ((W, "W"), (dW, "dW"), (m, "m"), (v, "v")):
+        _need(t, nm, torch.float32, W.numel())
+    check(lib.pairscreen_adam_step(_ptr(W), _ptr(dW), _ptr(m), _ptr(v), W.numel(), lr, b1, b2, eps, step,
+                                   _stream(stream)))
+
+
+def pairscreen_train(W, m, v, feats, y, steps: int, lr: float, step0: int = 0, *, stream=None):
+    """Full-batch training on the GPU; returns the per-step losses (device tensor)."""
+    lib = _lib.load()
+    n = feats.shape[0]
+    _need(feats, "feats", torch.float32, n * 5)
+    _need(y, "y", torch.float32, n)
+    for t, nm in ((W, "W"), (m, "m"), (v, "v")):
+        _need(t, nm, torch.float32, pairscreen_num_params())
+    losses = torch.empty(steps, dtype=torch.float32, device=feats.device)
+    nb = ctypes.c_size_t(0)
+    check(lib.pairscreen_train_workspace_size(n, ctypes.byref(nb)))
+    ws = _workspace(int(nb.value), feats.device, None)
+    check(lib.pairscreen_train(_ptr(W), _ptr(m), _ptr(v), _ptr(feats), _ptr(y), n, steps, step0, lr, _ptr(losses),
+                               _ptr(ws), ctypes.c_size_t(ws.numel()), _stream(stream)))
+    return losses
+
+
+def pairscreen_targets(pair_tnorm, log_scale, n_core: int, n_h: int, *, stream=None):
+    lib = _lib.load()
+    n_up = n_core * (n_core + 1) // 2
+    _need(pair_tnorm, "pair_tnorm", torch.float32, n_h * n_h)
+    _need(log_scale, "log_scale", torch.float64, 2 * n_up)
+    y = torch.empty(max(n_up, 1), dtype=torch.float32, device=pair_tnorm.device)
+    check(lib.pairscreen_targets(_ptr(pair_tnorm), _ptr(log_scale), n_core, n_h, _ptr(y), _stream(stream)))
+    return y[:n_up]
+
+
+def pairscreen_build_mask(pred, log_scale, n_core: int, n_h: int, threshold: float, margin: float = 0.0,
+                          mode: int = 0, *, stream=None):
+    """Returns (mask [n_h, n_h] uint8 on the device, number of dropped unordered pairs)."""
+    lib = _lib.load()
+    n_up = n_core * (n_core + 1) // 2
+    _need(log_scale, "log_scale", torch.float64, 2 * n_up)
+    if mode == 0:
+        _need(pred, "pred", torch.float32, n_up)
+    mask = torch.empty((n_h, n_h), dtype=torch.uint8, device=log_scale.device)
+    ws = torch.empty(256, dtype=torch.uint8, device=log_scale.device)
+    nd = ctypes.c_int64(0)
+    check(lib.pairscreen_build_mask(_ptr(pred) if mode == 0 else None, _ptr(log_scale), n_core, n_h, float(threshold),
+                                    float(margin), int(mode), _ptr(mask), ctypes.byref(nd), _ptr(ws),
+                                    ctypes.c_size_t(256), _stream(stream)))
+    return mask, int(nd.value)

@@ -29,6 +29,7 @@ SOURCES = [
     "split.hip",
     "pair_bf16.hip",
     "active.hip",
+    "screen.hip",
     "prof.cpp",
 ]
 

@@ -44,7 +44,7 @@ from typing import Optional
 
 import numpy as np
 
-__all__ = ["Inputs", "generate", "CONFIGS", "config_inputs", "input_recipe"]
+__all__ = ["Inputs", "generate", "CONFIGS", "config_inputs", "input_recipe", "mlp_init"]
 
 
 @dataclasses.dataclass
@@ -164,3 +164,14 @@ def config_inputs(name: str, seed: int = 0, **over) -> Inputs:
 
 def input_recipe() -> str:
     return __doc__
+
+
+def mlp_init(seed: int = 0, hidden: int = 64, n_in: int = 5) -> np.ndarray:
+    """Seeded initial parameters of the pair-screen network, packed as
+    [W1 (hidden x n_in), b1, W2 (hidden x hidden), b2, w3 (hidden), b3]:
+    weights ~ N(0, 1/fan_in), biases 0."""
+    rng = np.random.default_rng(seed)
+    W1 = rng.standard_normal((hidden, n_in)) / np.sqrt(n_in)
+    W2 = rng.standard_normal((hidden, hidden)) / np.sqrt(hidden)
+    w3 = rng.standard_normal(hidden) / np.sqrt(hidden)
+    return np.concatenate([W1.ravel(), np.zeros(hidden), W2.ravel(), np.zeros(hidden), w3, [0.0]])
