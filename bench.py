@@ -1,23 +1,30 @@
 #!/usr/bin/env python3
 """Benchmark of the DF-DSRG-PT2 virtual natural-orbital pass on one MI355X.
 
-A step is one pass of the whole hot path over one synthetic input set:
-    dfpt2_build_vv_density  (pair GEMM + DSRG epilogue + energy, density GEMM)
-    fno_truncate            (FP64 eigensolver, cumulative-ON threshold)
-    pt2_energy_correction   (recanonicalization, B transform, kept-space energy)
-Inputs are resident in HBM before the timed region starts.
+Metric: D_vv-build GFLOP/s and ms per pass of the mixed-precision, screened pass
+against the plain FP64 pass on the same GPU and inputs, with the energy error
+held to 1e-6 Eh.
 
-The reported value is the D_vv-build throughput in GFLOP/s counted with the
-nominal flop count F = n_aux n_v^2 n_h (n_h + 1) + 2 n_h^2 n_v^3 (the count used
-for every precision, so skipped work shows up as speed); ms_per_step is the
-whole step.  One JSON line goes to stdout.
+A step is one pass of the whole hot path over one synthetic input set (inputs
+resident in HBM before timing):
+    screen   pair features -> network -> mask            (learned pair screening)
+    build    dfpt2_build_vv_density (split B into BF16 slices, pair kernel with
+             fused DSRG epilogue and energy, density kernel), masked pairs skipped
+    fno      fno_truncate (FP64 eigensolver, cumulative-occupation threshold)
+    corr     pt2_energy_correction (recanonicalize, transform B, kept-space energy)
+value = F_nom / (screen + build time), F_nom = n_aux n_v^2 n_h(n_h+1) + 2 n_h^2 n_v^3,
+the same count for every precision (skipped work shows up as speed).
+Untimed setup: the screening network is trained on plain-pass labels of 200
+small (10 holes, 60 virtuals, 200 aux) input sets, and the plain FP64 pass on the
+workload is timed once as the reference the mixed pass is judged against.
 
-    python bench.py [--steps K] [--warmup W] [--workload c4] [--precision auto|fp64|bf16]
+    python bench.py [--steps K] [--warmup W] [--workload c4] [--precision bf16|fp64] [--no-screen]
 """
 from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import statistics
 import sys
@@ -28,16 +35,21 @@ sys.path.insert(0, ROOT)
 
 METRIC = "D_vv build GFLOP/s & ms/pass, mixed+screened vs FP64 at |ΔE|≤1e-6 Eh"
 PEAK_TFLOPS = {"f64": 78.6, "bf16": 2500.0, "fp8": 5000.0}
+SCREEN_THRESHOLD = 1e-6
+
+WORKLOADS = {
+    # the literal screened workload: c3 sizes, plain generator
+    "c4": dict(base="c4", gen=dict()),
+    # localized variant of the same sizes (hole/aux positions, xi = 1.25) where pairs decay
+    "c4loc": dict(base="c4", gen=dict(localized_xi=1.25)),
+    "c3": dict(base="c3", gen=dict()),
+    "c2": dict(base="c2", gen=dict(low_rank=64)),
+    "c5": dict(base="c5", gen=dict()),
+}
 
 
 def nominal_flops(n_h, n_v, n_aux):
     return n_aux * n_v * n_v * n_h * (n_h + 1) + 2 * n_h * n_h * n_v ** 3
-
-
-def pair_kernel_flops(n_core, n_v, n_aux, products):
-    """Flops issued by the pair kernel for one pass: every unordered core pair
-    costs 2 n_v^2 n_aux per operand-slice product."""
-    return products * 2.0 * n_v * n_v * n_aux * (n_core * (n_core + 1) // 2)
 
 
 def load_golden(workload, s):
@@ -49,9 +61,13 @@ def load_golden(workload, s):
         return json.load(f)
 
 
+def dd(a, b):
+    return abs(math.fsum([a[0], a[1], -b[0], -b[1]]))
+
+
 def cpu_baseline(inp, s, target_seconds=15.0):
-    """Time the FP64 oracle on the first k core holes of the same workload
-    (full n_v and n_aux), k chosen for ~target_seconds of work."""
+    """The FP64 oracle on the first k core holes of the same workload (full n_v and
+    n_aux), k chosen for about target_seconds of work; nominal flops / wall time."""
     from oracle import dsrg_pt2 as o
     import numpy as np
     try:
@@ -68,7 +84,7 @@ def cpu_baseline(inp, s, target_seconds=15.0):
         o.pt2_pass_inputs(sub, s)
         return time.perf_counter() - t0
 
-    run(1)                      # warm the BLAS thread pool
+    run(1)
     t2 = run(2)
     per_pair = max(t2 / 4.0, 1e-4)
     k = int(max(2, min(inp.n_core, (target_seconds / per_pair) ** 0.5)))
@@ -79,63 +95,111 @@ def cpu_baseline(inp, s, target_seconds=15.0):
                       f"at n_v={nv}, n_aux={na} ({k * k} ordered pairs, {dt:.1f} s); nominal flops / wall time"}
 
 
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="c4")
-    ap.add_argument("--precision", default="auto")
+    ap.add_argument("--workload", default="c4", choices=sorted(WORKLOADS))
+    ap.add_argument("--precision", default="bf16", choices=["bf16", "fp64"])
+    ap.add_argument("--no-screen", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64-ref", action="store_true")
     ap.add_argument("--s", type=float, default=None)
     ap.add_argument("--p-o", type=float, default=None)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--compare-fp64", action="store_true", help="also time the FP64 pass (extra minutes)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
-              "(the pass shards over hole pairs with one D_vv all-reduce, not built here)", file=sys.stderr)
+        print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported (the pass would "
+              "shard hole pairs over GPUs with one D_vv all-reduce, which is not built here)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
     import torch
     import synth
     import paper_2312_07008_amd as dp
+    from paper_2312_07008_amd import screening
 
-    cfg = synth.CONFIGS[args.workload]
+    wl = WORKLOADS[args.workload]
+    cfg = synth.CONFIGS[wl["base"]]
     s = args.s if args.s is not None else cfg["s"][0]
     p_o = args.p_o if args.p_o is not None else cfg["p_o"][0]
-    prec_name = args.precision
-    if prec_name == "auto":
-        prec_name = "fp64"
-    prec = {"fp64": dp.FP64, "bf16": dp.BF16_SLICED, "fp8": dp.FP8_SLICED}[prec_name]
-    dtype = {"fp64": "f64", "bf16": "bf16", "fp8": "fp8"}[prec_name]
+    prec = {"fp64": dp.FP64, "bf16": dp.BF16_SLICED}[args.precision]
+    dtype = {"fp64": "f64", "bf16": "bf16"}[args.precision]
+    screen = not args.no_screen
 
     t0 = time.time()
-    inp = synth.config_inputs(args.workload)
-    print(f"[bench] inputs {args.workload} {cfg['sizes']} generated in {time.time() - t0:.1f} s", file=sys.stderr,
-          flush=True)
+    n_core, n_act, n_v, n_aux = cfg["sizes"]
+    inp = synth.generate(n_core, n_act, n_v, n_aux, 0, label=args.workload, **wl["gen"])
+    log(f"inputs {args.workload} {cfg['sizes']} {wl['gen']} generated in {time.time() - t0:.1f} s")
     d = dp.upload_inputs(inp)
-    n_core, n_act, n_v, n_aux, n_h = inp.n_core, inp.n_act, inp.n_vir, inp.n_aux, inp.n_h
+    n_h = inp.n_h
     opts = dp.make_opts(n_core, n_act, n_v, n_aux, s, precision=prec)
+    stream = torch.cuda.current_stream()
+
+    # ---- untimed setup: train the screen on small plain-pass labels
+    W = None
+    margin = 0.0
+    train_info = None
+    if screen:
+        t0 = time.time()
+        tr_inputs = (synth.generate(10, 0, 60, 200, seed=k,
+                                    localized_xi=(None if k % 2 else 0.6 + 2.4 * ((k * 37) % 97) / 97.0))
+                     for k in range(1, 201))
+        X, Y = screening.collect(tr_inputs, s)
+        W, losses, margin = screening.train(X, Y, synth.mlp_init(0), steps=1500, lr=3e-3)
+        torch.cuda.synchronize()
+        train_info = {"samples": int(X.shape[0]), "steps": 1500, "final_mse": float(losses[-1].item()),
+                      "margin_log": margin, "seconds": time.time() - t0}
+        log(f"screen trained on {X.shape[0]} pairs: mse {train_info['final_mse']:.4f}, {train_info['seconds']:.1f} s")
+
+    # ---- untimed reference: the plain FP64 pass on the same inputs
+    ref = None
+    if not args.no_fp64_ref:
+        o64 = dp.make_opts(n_core, n_act, n_v, n_aux, s, precision=dp.FP64)
+        ws64 = torch.empty(dp.workspace_size(o64), dtype=torch.uint8, device="cuda")
+        times = []
+        for it in range(2):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            r64 = dp.build_vv_density(o64, d["eps_hole"], d["eps_vir"], d["gamma_act"], d["B"], workspace=ws64,
+                                      stream=stream)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            times.append(e0.elapsed_time(e1))
+        t64 = dp.fno_truncate(r64["D_vv"], p_o)
+        ref = {"ms": min(times), "E": r64["e_pt2"].cpu().numpy(), "occ": t64["occ"].cpu().numpy(),
+               "n_kept": t64["n_kept"]}
+        del ws64, r64, t64
+        torch.cuda.empty_cache()
+        log(f"FP64 reference pass {ref['ms']:.1f} ms, kept {ref['n_kept']}")
+
     ws_pass = torch.empty(dp.workspace_size(opts), dtype=torch.uint8, device="cuda")
     ws_fno = torch.empty(dp.fno_truncate_workspace_size(n_v), dtype=torch.uint8, device="cuda")
     ws_corr = torch.empty(dp.pt2_correction_workspace_size(opts, n_v), dtype=torch.uint8, device="cuda")
     D = torch.empty((n_v, n_v), dtype=torch.float64, device="cuda")
     e = torch.empty(2, dtype=torch.float64, device="cuda")
-    stream = torch.cuda.current_stream()
 
     def step():
-        ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
         ev[0].record(stream)
-        dp.build_vv_density(opts, d["eps_hole"], d["eps_vir"], d["gamma_act"], d["B"], D_vv=D, e_pt2=e,
-                            workspace=ws_pass, stream=stream)
+        mask, nd = None, 0
+        if screen:
+            mask, nd = screening.predict_mask(W, opts, d["eps_hole"], d["eps_vir"], d["B"], SCREEN_THRESHOLD, margin,
+                                              stream=stream)
         ev[1].record(stream)
-        tr = dp.fno_truncate(D, p_o, workspace=ws_fno, stream=stream)
+        dp.build_vv_density(opts, d["eps_hole"], d["eps_vir"], d["gamma_act"], d["B"], mask, D_vv=D, e_pt2=e,
+                            workspace=ws_pass, stream=stream)
         ev[2].record(stream)
+        tr = dp.fno_truncate(D, p_o, workspace=ws_fno, stream=stream)
+        ev[3].record(stream)
         c = dp.pt2_energy_correction(opts, d["eps_hole"], d["eps_vir"], d["gamma_act"], d["B"], tr["no_vecs"],
                                      tr["n_kept"], e, workspace=ws_corr, stream=stream)
-        ev[3].record(stream)
-        return ev, tr, c
+        ev[4].record(stream)
+        return ev, tr, c, nd
 
     for _ in range(args.warmup):
         step()
@@ -149,56 +213,69 @@ def main():
     prof = dp.profile_read()
     dp.profile_enable(False)
 
-    build_ms = [r[0][0].elapsed_time(r[0][1]) for r in records]
-    fno_ms = [r[0][1].elapsed_time(r[0][2]) for r in records]
-    corr_ms = [r[0][2].elapsed_time(r[0][3]) for r in records]
+    def med(i, j):
+        return statistics.median(r[0][i].elapsed_time(r[0][j]) for r in records)
+
+    screen_ms, build_ms, fno_ms, corr_ms = med(0, 1), med(1, 2), med(2, 3), med(3, 4)
+    ms_pass = screen_ms + build_ms
     ms_per_step = 1e3 * t_total / args.steps
-    ms_pass = statistics.median(build_ms)
     F = nominal_flops(n_h, n_v, n_aux)
     value = F / (ms_pass * 1e-3) / 1e9
 
-    # dominant kernel: the pair kernel (GEMM1 + fused epilogue)
-    products = 1
+    # dominant kernel: the pair kernel (V = B_i B_j^T + fused epilogue); issued MFMA flops:
+    # 2 n_v^2 n_aux per computed unordered core pair and per operand-slice product
+    ns1 = 4 if args.precision == "bf16" else 1
+    products = ns1 * (ns1 + 1) // 2
+    tr, c, nd = records[-1][1], records[-1][2], records[-1][3]
+    n_up = n_core * (n_core + 1) // 2
+    computed = n_up - nd
     pk_ms, pk_launch = prof["pair"]
-    passes = args.steps
-    pk_flops_per_pass = pair_kernel_flops(n_core, n_v, n_aux, products)
-    launches_per_pass = max(1, pk_launch // passes)
-    achieved = pk_flops_per_pass * passes / (pk_ms * 1e-3) / 1e12 if pk_launch else None
+    achieved = (products * 2.0 * n_v * n_v * n_aux * computed * args.steps) / (pk_ms * 1e-3) / 1e12 if pk_launch else None
     peak = PEAK_TFLOPS[dtype]
     roofline = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                 "frac": (achieved / peak) if achieved else None, "traffic": None,
-                "kernel": "pair_gemm (V = B_i B_j^T + DSRG epilogue)",
+                "kernel": f"pair_gemm_{'bf16' if ns1 > 1 else 'f64'} (V = B_i B_j^T, {products} slice products, "
+                          "fused DSRG epilogue)",
                 "kernel_ms_per_launch": pk_ms / pk_launch if pk_launch else None,
-                "launches_per_pass": launches_per_pass}
+                "launches_per_pass": pk_launch // args.steps if pk_launch else 0,
+                "flops_per_unit": f"{products} x 2 n_v^2 n_aux per computed unordered core pair"}
 
-    tr, c = records[-1][1], records[-1][2]
     E = e.cpu().numpy()
     corr = c["correction"].cpu().numpy()
+    occ = tr["occ"].cpu().numpy()
     out = {"metric": METRIC, "value": value, "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": dtype, "data": "synthetic",
-           "config": {"workload": f"{args.workload}: closed/active DF-DSRG-PT2 virtual NO pass",
+           "config": {"workload": f"{args.workload}: DF-DSRG-PT2 virtual-NO pass, {wl['gen'] or 'plain'} inputs",
                       "n_core": n_core, "n_act": n_act, "n_vir": n_v, "n_aux": n_aux, "s": s, "p_o": p_o,
-                      "precision": prec_name, "screening": False},
-           "ms_per_pass": ms_pass, "stage_ms_per_step": {"build": statistics.median(build_ms),
-                                                         "fno_truncate": statistics.median(fno_ms),
-                                                         "correction": statistics.median(corr_ms)},
-           "kernel_ms_per_step": {k: v[0] / passes for k, v in prof.items() if v[1]},
-           "nominal_gflop_per_pass": F / 1e9,
+                      "precision": args.precision, "slices": ns1, "screening": screen,
+                      "screen_threshold": SCREEN_THRESHOLD if screen else None},
+           "ms_per_pass": ms_pass,
+           "stage_ms_per_step": {"screen": screen_ms, "build": build_ms, "fno_truncate": fno_ms,
+                                 "correction": corr_ms},
+           "kernel_ms_per_step": {k: v[0] / args.steps for k, v in prof.items() if v[1]},
+           "nominal_gflop_per_pass": F / 1e9, "pairs_dropped": nd, "pairs_total": n_up,
            "n_kept": tr["n_kept"], "margins": list(tr["margins"]),
            "E_pt2": [float(E[0]), float(E[1])], "correction": [float(corr[0]), float(corr[1])],
            "roofline": roofline}
+    if train_info:
+        out["screen_training"] = train_info
+    if ref is not None:
+        out["fp64_ms_per_pass"] = ref["ms"]
+        out["speedup_vs_fp64"] = ref["ms"] / ms_pass
+        out["delta_E_vs_fp64_Eh"] = dd((float(E[0]), float(E[1])), (float(ref["E"][0]), float(ref["E"][1])))
+        out["max_dON_vs_fp64"] = float(np.abs(occ - ref["occ"]).max())
+        out["n_kept_fp64"] = ref["n_kept"]
     gold = load_golden(args.workload, s)
     if gold is not None:
-        import math
-        out["delta_E_vs_oracle_Eh"] = abs(math.fsum([E[0], E[1], -gold["energy"][0], -gold["energy"][1]]))
+        out["delta_E_vs_oracle_Eh"] = dd((float(E[0]), float(E[1])), gold["energy"])
         g_tr = [t for t in gold["truncation"] if abs(t["p_o"] - p_o) < 1e-12]
         if g_tr:
             out["n_kept_oracle"] = g_tr[0]["n_kept"]
-            out["delta_correction_vs_oracle_Eh"] = abs(math.fsum([corr[0], corr[1], -g_tr[0]["correction"][0],
-                                                                  -g_tr[0]["correction"][1]]))
+            out["delta_correction_vs_oracle_Eh"] = dd((float(corr[0]), float(corr[1])), g_tr[0]["correction"])
+        out["max_dON_vs_oracle"] = float(np.abs(occ - np.array(gold["occ"])).max())
     if not args.no_cpu_baseline:
-        print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
+        log("timing the CPU oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(inp, s)
     print(json.dumps(out), flush=True)
 
