@@ -111,6 +111,9 @@ def main():
     ap.add_argument("--no-fp64-ref", action="store_true")
     ap.add_argument("--s", type=float, default=None)
     ap.add_argument("--p-o", type=float, default=None)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="run one device-to-device copy of this many MiB before timing (a reference "
+                         "kernel of known traffic for hardware-counter runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported (the pass would "
@@ -176,6 +179,15 @@ def main():
         del ws64, r64, t64
         torch.cuda.empty_cache()
         log(f"FP64 reference pass {ref['ms']:.1f} ms, kept {ref['n_kept']}")
+
+    if args.copy_calibration:
+        nbytes = args.copy_calibration << 20
+        src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"calibration copy of {nbytes} bytes done")
+        del src, dst
 
     ws_pass = torch.empty(dp.workspace_size(opts), dtype=torch.uint8, device="cuda")
     ws_fno = torch.empty(dp.fno_truncate_workspace_size(n_v), dtype=torch.uint8, device="cuda")

@@ -71,7 +71,7 @@ typedef struct dfpt2_opts {
   int64_t n_aux;    /* auxiliary (density-fitting) functions */
   double  s;        /* DSRG flow parameter s (Eh^-2), > 0 */
   int32_t precision;          /* dfpt2_precision */
-  int32_t slices_gemm1;       /* slices per operand of V = B B^T; 0 = precision default */
+  int32_t slices_gemm1;       /* slices per operand of V = B B^T; 0 = precision default (BF16: 4, range 2..4) */
   int32_t slices_gemm2;       /* slices per operand of the density product; 0 = default */
   int32_t density_convention; /* 0: spin-summed Gamma^(2)_vv (Eq. A9); 1: per spin (half) */
   int64_t pair_batch;         /* unordered pairs per batch; 0 = library default */

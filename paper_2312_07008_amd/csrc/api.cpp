@@ -86,8 +86,8 @@ int plan_pass(const dfpt2_opts* o, PassPlan* pl, bool energy_only) {
   p.ns1 = o->slices_gemm1 ? o->slices_gemm1 : default_slices_gemm1(o->precision);
   p.n_v_pad = (p.n_v + 63) / 64 * 64;
   p.n_aux_pad = (p.n_aux + 15) / 16 * 16;
-  if (p.precision == DFPT2_BF16_SLICED && (p.ns1 < 2 || p.ns1 > 5))
-    return fail(DFPT2_ERR_INVALID_ARG, "slices_gemm1 must lie in [2, 5] for BF16 slicing");
+  if (p.precision == DFPT2_BF16_SLICED && (p.ns1 < 2 || p.ns1 > 4))
+    return fail(DFPT2_ERR_INVALID_ARG, "slices_gemm1 must lie in [2, 4] for BF16 slicing");
 
   size_t off = 0;
   auto take = [&](size_t bytes) {

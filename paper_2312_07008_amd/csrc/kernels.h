@@ -33,6 +33,7 @@ struct PairBf16Args {
   double* epart;
   double* tpart;
   int n_v, n_v_pad, n_aux_pad, nt, nTP;
+  int n_blk_pairs;      // pairs of this launch (set by the launcher)
   double s;
   double e_weight;
 };

