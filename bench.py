@@ -95,6 +95,32 @@ def cpu_baseline(inp, s, target_seconds=15.0):
                       f"at n_v={nv}, n_aux={na} ({k * k} ordered pairs, {dt:.1f} s); nominal flops / wall time"}
 
 
+def recorded_traffic(kernel: str, workload: str):
+    """HBM-side bytes per launch of `kernel` on `workload` from a committed hardware-counter
+    summary under profiles/ (FETCH_SIZE and WRITE_SIZE, each scaled by what the same counter
+    reads for a device copy of known size).  None if there is no record, or if the kernel's
+    sources have changed since the counters were taken (recorded SHA-256 of the sources)."""
+    import glob
+    import hashlib
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
+        with open(path) as f:
+            for line in f:
+                if not line.startswith("traffic-record:"):
+                    continue
+                kv = dict(t.split("=", 1) for t in line.split()[1:])
+                if kv.get("kernel") != kernel or kv.get("workload") != workload:
+                    continue
+                h = hashlib.sha256()
+                for src in kv["sources"].split(","):
+                    with open(os.path.join(ROOT, src), "rb") as g:
+                        h.update(g.read())
+                if h.hexdigest() != kv["sha256"]:
+                    return None
+                return 1024.0 * (float(kv["fetch_kib"]) * float(kv["fetch_scale"]) +
+                                 float(kv["write_kib"]) * float(kv["write_scale"]))
+    return None
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -242,12 +268,17 @@ def main():
     n_up = n_core * (n_core + 1) // 2
     computed = n_up - nd
     pk_ms, pk_launch = prof["pair"]
+    screen_drops = nd > 0  # a different set of launches than the counters were taken on
     achieved = (products * 2.0 * n_v * n_v * n_aux * computed * args.steps) / (pk_ms * 1e-3) / 1e12 if pk_launch else None
     peak = PEAK_TFLOPS[dtype]
     roofline = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                "frac": (achieved / peak) if achieved else None, "traffic": None,
+                "frac": (achieved / peak) if achieved else None,
+                "traffic": recorded_traffic(f"pair_gemm_bf16_kernel<{ns1},true>", args.workload)
+                if (ns1 > 1 and not screen_drops) else None,
                 "kernel": f"pair_gemm_{'bf16' if ns1 > 1 else 'f64'} (V = B_i B_j^T, {products} slice products, "
                           "fused DSRG epilogue)",
+                "traffic_unit": "HBM-side bytes per launch: FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 (factors from a "
+                                "1 GiB device copy), from the committed counter summary under profiles/",
                 "kernel_ms_per_launch": pk_ms / pk_launch if pk_launch else None,
                 "launches_per_pass": pk_launch // args.steps if pk_launch else 0,
                 "flops_per_unit": f"{products} x 2 n_v^2 n_aux per computed unordered core pair"}
