@@ -28,6 +28,7 @@ SOURCES = [
     "correction.cpp",
     "split.hip",
     "pair_bf16.hip",
+    "pair_fp8.hip",
     "active.hip",
     "screen.hip",
     "prof.cpp",

@@ -85,9 +85,9 @@ int plan_pass(const dfpt2_opts* o, PassPlan* pl, bool energy_only) {
   p.precision = o->precision;
   p.ns1 = o->slices_gemm1 ? o->slices_gemm1 : default_slices_gemm1(o->precision);
   p.n_v_pad = (p.n_v + 63) / 64 * 64;
-  p.n_aux_pad = (p.n_aux + 15) / 16 * 16;
-  if (p.precision == DFPT2_BF16_SLICED && (p.ns1 < 2 || p.ns1 > 4))
-    return fail(DFPT2_ERR_INVALID_ARG, "slices_gemm1 must lie in [2, 4] for BF16 slicing");
+  p.n_aux_pad = p.precision == DFPT2_FP8_SLICED ? (p.n_aux + 63) / 64 * 64 : (p.n_aux + 15) / 16 * 16;
+  if (p.precision != DFPT2_FP64 && (p.ns1 < 2 || p.ns1 > 4))
+    return fail(DFPT2_ERR_INVALID_ARG, "slices_gemm1 must lie in [2, 4] for BF16 and FP8 slicing");
 
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -103,10 +103,11 @@ int plan_pass(const dfpt2_opts* o, PassPlan* pl, bool energy_only) {
   p.off_pe = take(sizeof(double) * 2 * (size_t)(p.n_up > 0 ? p.n_up : 1));
   p.off_tn2 = take(sizeof(double) * (size_t)(p.n_up > 0 ? p.n_up : 1));
   p.off_Dpart = take(energy_only ? 0 : sizeof(double) * mat * p.nsplit);
-  p.off_Bs = take(p.precision == DFPT2_BF16_SLICED
-                      ? (size_t)p.ns1 * p.n_h * p.n_v_pad * p.n_aux_pad * sizeof(__bf16)
-                      : 0);
-  p.off_norm2 = take(p.precision == DFPT2_BF16_SLICED ? sizeof(double) * (size_t)p.n_h * p.n_v : 0);
+  const size_t slice_bytes = p.precision == DFPT2_BF16_SLICED ? sizeof(__bf16) : p.precision == DFPT2_FP8_SLICED ? 1 : 0;
+  p.off_Bs = take(slice_bytes * p.ns1 * p.n_h * p.n_v_pad * p.n_aux_pad);
+  p.off_scales = take(p.precision == DFPT2_FP8_SLICED ? sizeof(uint32_t) * 2 * (size_t)p.n_h * p.n_v_pad * (p.n_aux_pad / 64)
+                                                      : 0);
+  p.off_norm2 = take(p.precision != DFPT2_FP64 ? sizeof(double) * (size_t)p.n_h * p.n_v : 0);
   // active holes: stacked amplitude/integral matrices before and after the rotation
   p.n_ca = p.n_core * p.n_act;
   p.n_aa_un = p.n_act * (p.n_act + 1) / 2;
@@ -190,8 +191,6 @@ int dfpt2_build_vv_density(const dfpt2_opts* opts, const double* eps_hole, const
   if (!workspace && pl.ws_bytes) return fail(DFPT2_ERR_INVALID_ARG, "workspace is null");
   if (ws_bytes < pl.ws_bytes)
     return fail(DFPT2_ERR_WORKSPACE, "workspace has %zu bytes, %zu needed", ws_bytes, pl.ws_bytes);
-  if (opts->precision == DFPT2_FP8_SLICED)
-    return fail(DFPT2_ERR_UNSUPPORTED, "precision %d is not supported by this build", opts->precision);
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   return run_pass(pl, *opts, eps_hole, eps_vir, gamma_act, B, pair_mask, D_vv, e_pt2, pair_energy, pair_tnorm,
                   static_cast<char*>(workspace), s);
@@ -201,13 +200,13 @@ int dfpt2_build_vv_density(const dfpt2_opts* opts, const double* eps_hole, const
 
 namespace dfpt2 {
 
-int default_slices_gemm1(int precision) { return precision == DFPT2_BF16_SLICED ? 4 : 1; }
+int default_slices_gemm1(int precision) { return precision == DFPT2_FP64 ? 1 : 4; }
 
 hipError_t launch_pair(const PairLaunch& L, const PairKernelArgs& a, int n_pairs, hipStream_t st) {
   if (L.precision == DFPT2_FP64) return launch_pair_gemm_f64(a, n_pairs, st);
-  PairBf16Args b{};
+  PairSlicedArgs b{};
   b.Bs = L.Bs;
-  b.slice_stride = L.slice_stride;
+  b.scales = L.scales;
   b.norm2 = L.norm2;
   b.eps_h = a.eps_h;
   b.eps_v = a.eps_v;
@@ -223,7 +222,8 @@ hipError_t launch_pair(const PairLaunch& L, const PairKernelArgs& a, int n_pairs
   b.nTP = a.nTP;
   b.s = a.s;
   b.e_weight = a.e_weight;
-  return launch_pair_gemm_bf16(b, L.ns, n_pairs, st);
+  return L.precision == DFPT2_FP8_SLICED ? launch_pair_gemm_fp8(b, L.ns, n_pairs, st)
+                                         : launch_pair_gemm_bf16(b, L.ns, n_pairs, st);
 }
 
 // Active blocks of the pass (row a6): core-active pairs in batches of cores, then
@@ -368,17 +368,23 @@ int run_pass(const PassPlan& pl, const dfpt2_opts& o, const double* eps_h, const
   double* Dpart = reinterpret_cast<double*>(ws + pl.off_Dpart);
   const size_t mat = (size_t)pl.n_v * pl.n_v;
 
-  PairLaunch L{pl.precision, pl.ns1, B, nullptr, 0, pl.n_v_pad, pl.n_aux_pad, nullptr};
-  if (pl.precision == DFPT2_BF16_SLICED) {
+  PairLaunch L{pl.precision, pl.ns1, B, nullptr, nullptr, pl.n_v_pad, pl.n_aux_pad, nullptr};
+  if (pl.precision != DFPT2_FP64) {
     ProfScope ps(DFPT2_STAGE_SPLIT, s);
-    __bf16* Bs = reinterpret_cast<__bf16*>(ws + pl.off_Bs);
-    L.Bs = Bs;
-    L.slice_stride = (long long)pl.n_h * pl.n_v_pad * pl.n_aux_pad;
     double* nrm = reinterpret_cast<double*>(ws + pl.off_norm2);
     L.norm2 = nrm;
-    if ((e = launch_split_rows_bf16(B, pl.n_aux, pl.n_h, pl.n_v, pl.n_v_pad, pl.n_aux, pl.n_aux_pad, pl.ns1, Bs,
-                                    nrm, s)) != hipSuccess)
-      return hip_fail(e, "split");
+    L.Bs = ws + pl.off_Bs;
+    if (pl.precision == DFPT2_BF16_SLICED) {
+      if ((e = launch_split_rows_bf16(B, pl.n_aux, pl.n_h, pl.n_v, pl.n_v_pad, pl.n_aux, pl.n_aux_pad, pl.ns1,
+                                      reinterpret_cast<__bf16*>(ws + pl.off_Bs), nrm, s)) != hipSuccess)
+        return hip_fail(e, "split");
+    } else {
+      uint32_t* sc = reinterpret_cast<uint32_t*>(ws + pl.off_scales);
+      L.scales = sc;
+      if ((e = launch_split_rows_fp8(B, pl.n_aux, pl.n_h, pl.n_v, pl.n_v_pad, pl.n_aux, pl.n_aux_pad, pl.ns1,
+                                     reinterpret_cast<uint8_t*>(ws + pl.off_Bs), sc, nrm, s)) != hipSuccess)
+        return hip_fail(e, "split");
+    }
   }
   {
     ProfScope ps(DFPT2_STAGE_REDUCE, s);

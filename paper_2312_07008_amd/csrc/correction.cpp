@@ -112,8 +112,6 @@ int pt2_energy_correction(const dfpt2_opts* opts, const double* eps_hole, const 
     return fail(DFPT2_ERR_INVALID_ARG, "null pointer argument");
   if (opts->n_act > 0 && !gamma_act) return fail(DFPT2_ERR_INVALID_ARG, "gamma_act is null but n_act > 0");
   if (ws_bytes < cp.total) return fail(DFPT2_ERR_WORKSPACE, "workspace has %zu bytes, %zu needed", ws_bytes, cp.total);
-  if (opts->precision == DFPT2_FP8_SLICED)
-    return fail(DFPT2_ERR_UNSUPPORTED, "precision %d is not supported by this build", opts->precision);
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   char* ws = static_cast<char*>(workspace);
   double* Y = (double*)(ws + cp.off_Y);

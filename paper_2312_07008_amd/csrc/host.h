@@ -27,7 +27,7 @@ struct PassPlan {
   bool energy_only; // no amplitudes stored, no density (kept-space energy)
   int ns1;          // slices per operand of the pair product (mixed precision)
   int n_v_pad, n_aux_pad;
-  size_t off_pairs, off_count, off_T, off_epart, off_tpart, off_pe, off_tn2, off_Dpart, off_Bs, off_norm2;
+  size_t off_pairs, off_count, off_T, off_epart, off_tpart, off_pe, off_tn2, off_Dpart, off_Bs, off_scales, off_norm2;
   // active holes
   int n_ca, n_aa_un, cpb, act_cap;
   size_t off_act_T, off_act_V, off_act_Tr, off_act_Vr, off_act_pairs, off_act_slots, off_act_pairs2,
@@ -44,12 +44,13 @@ int run_pass(const PassPlan& pl, const dfpt2_opts& o, const double* eps_h, const
              double* pair_energy, float* pair_tnorm, char* ws, hipStream_t s);
 
 // Pair-kernel launcher shared by the pass and the kept-space energy: FP64, or
-// split BF16 from the slices in `Bs` (prepared by the caller).
+// split BF16 / FP8 from the slices in `Bs` (and FP8 block scales in `scales`),
+// prepared by the caller.
 struct PairLaunch {
   int precision, ns;
   const double* B;
-  const __bf16* Bs;
-  long long slice_stride;
+  const void* Bs;
+  const uint32_t* scales;
   int n_v_pad, n_aux_pad;
   const double* norm2;
 };

@@ -20,10 +20,11 @@ struct PairKernelArgs {
 };
 hipError_t launch_pair_gemm_f64(const PairKernelArgs& a, int n_pairs, hipStream_t st);
 
-// -------------------------------------------------------- split-BF16 pair kernel
-struct PairBf16Args {
-  const __bf16* Bs;     // [n_h][n_v_pad][n_aux_pad/16][ns][16] BF16 slices (split.hip)
-  long long slice_stride;  // unused with the chunk-interleaved layout
+// ------------------------------------------------ sliced (BF16 / FP8) pair kernels
+struct PairSlicedArgs {
+  const void* Bs;       // BF16: [n_h][n_v_pad][n_aux_pad/16][ns][16] slices (split.hip)
+                        // FP8:  [n_h][n_v_pad][n_aux_pad/64][ns][64] e4m3 slices (split.hip)
+  const uint32_t* scales;  // FP8 only: [n_h][n_v_pad][n_aux_pad/64][2] E8M0 scale words
   const double* norm2;  // [n_h][n_v] ||B_ia||^2 in FP64: exact diagonal of V^{ii}
   const double* eps_h;
   const double* eps_v;
@@ -37,10 +38,14 @@ struct PairBf16Args {
   double s;
   double e_weight;
 };
-hipError_t launch_pair_gemm_bf16(const PairBf16Args& a, int ns, int n_pairs, hipStream_t st);
-// FP64 rows -> BF16 slices, see split.hip
+hipError_t launch_pair_gemm_bf16(const PairSlicedArgs& a, int ns, int n_pairs, hipStream_t st);
+hipError_t launch_pair_gemm_fp8(const PairSlicedArgs& a, int ns, int n_pairs, hipStream_t st);
+// FP64 rows -> BF16 / FP8 slices, see split.hip
 hipError_t launch_split_rows_bf16(const double* X, long long ldx, int nb, int rows, int rows_pad, int ncols,
                                   int ncols_pad, int ns, __bf16* out, double* norm2, hipStream_t st);
+hipError_t launch_split_rows_fp8(const double* X, long long ldx, int nb, int rows, int rows_pad, int ncols,
+                                 int ncols_pad, int ns, uint8_t* out, uint32_t* scales, double* norm2,
+                                 hipStream_t st);
 
 // ------------------------------------------------------------- density kernel
 struct DensityKernelArgs {

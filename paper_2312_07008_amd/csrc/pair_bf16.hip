@@ -64,7 +64,7 @@ __device__ inline int xcd_block(int h, int nblk) {
 }  // namespace
 
 template <int NS, bool STORE>
-__global__ __launch_bounds__(256, 2) void pair_gemm_bf16_kernel(PairBf16Args a) {
+__global__ __launch_bounds__(256, 2) void pair_gemm_bf16_kernel(PairSlicedArgs a) {
   static_assert(2 * NS <= SLOTS, "slices per LDS row");
   __shared__ u4 lds0[4 * PANEL_U4];
   __shared__ u4 lds1[4 * PANEL_U4];
@@ -89,7 +89,7 @@ __global__ __launch_bounds__(256, 2) void pair_gemm_bf16_kernel(PairBf16Args a) 
   const int tile_w = (q_w == 0 || q_w == 2) ? I : J;
   const bool load_w = q_w < npanel;
   const int row_bytes = a.n_aux_pad * NS * 2;
-  const char* panel = reinterpret_cast<const char*>(a.Bs) + ((size_t)hole_w * a.n_v_pad + tile_w * TM) * row_bytes;
+  const char* panel = static_cast<const char*>(a.Bs) + ((size_t)hole_w * a.n_v_pad + tile_w * TM) * row_bytes;
   // row 8 m + l/8 of the panel, logical slot (l % 8) ^ f(row) = (l % 8) ^ (l / 8) ^ m
   const int l3 = lane >> 3, l7 = lane & 7;
   auto src_off = [&](int m) -> uint32_t {
@@ -241,10 +241,10 @@ __global__ __launch_bounds__(256, 2) void pair_gemm_bf16_kernel(PairBf16Args a) 
   }
 }
 
-hipError_t launch_pair_gemm_bf16(const PairBf16Args& a, int ns, int n_pairs, hipStream_t st) {
+hipError_t launch_pair_gemm_bf16(const PairSlicedArgs& a, int ns, int n_pairs, hipStream_t st) {
   if (n_pairs <= 0) return hipSuccess;
   if ((long long)a.nTP * n_pairs > 0x7fffffffLL) return hipErrorInvalidValue;
-  PairBf16Args b = a;
+  PairSlicedArgs b = a;
   b.n_blk_pairs = n_pairs;
   dim3 grid(a.nTP * n_pairs), block(256);
   const bool store = a.T != nullptr || a.Vr != nullptr;

@@ -76,4 +76,87 @@ hipError_t launch_split_rows_bf16(const double* X, long long ldx, int nb, int ro
   return hipGetLastError();
 }
 
+
+// ------------------------------------------------------------------ FP8 slices
+// FP8 (OCP e4m3) operands with per-block power-of-two scales: every 32-wide block
+// of a row (32 consecutive auxiliary functions of one virtual of one hole) is
+// split on its own, relative to the block's largest magnitude m = f 2^E:
+//     y = x 2^(4 - E)               (|y| < 16)
+//     s_1 = rint(y),  r_1 = y - s_1            (|s_1| <= 16, |r_1| <= 1/2)
+//     s_t = rint(32 r_{t-1}), r_t = 32 r_{t-1} - s_t   (|s_t| <= 16)
+// Integers of magnitude <= 16 are exact in e4m3; slice t of the block carries the
+// E8M0 scale 2^(E - 4 - 5 (t - 1)), applied by the scaled MFMA.  So x = sum_t
+// s_t 2^(E - 4 - 5(t-1)) + O(2^(E - 5 k)) per element: about 5 bits per slice.
+//
+// Layout, chosen for the lane layout of the 32x32x64 scaled MFMA (a lane of half
+// h holds the 16-element groups h and 2 + h of a 64-wide chunk, and the scale of
+// K-block h comes from that half):
+//   out:    [nb][rows_pad][ncols_pad/64][ns][64] bytes; within one slice of one
+//           chunk, element kk (0..63) sits at 32 ((kk % 32) / 16) + (kk % 16) + 16 (kk / 32)
+//   scales: [nb][rows_pad][ncols_pad/64][2] words; byte t of word h is the E8M0
+//           scale of slice t of K-block h (ns <= 4)
+// Blocks whose largest magnitude is below 2^-100 (E8M0 underflow of trailing
+// slices) keep only the slices whose scale is representable.
+namespace {
+__device__ inline uint32_t e4m3_of_int(int n) {  // |n| <= 16, exact
+  if (n == 0) return 0u;
+  const uint32_t sgn = n < 0 ? 0x80u : 0u;
+  const int m = n < 0 ? -n : n;
+  const int k = 31 - __clz(m);                  // floor(log2 m), 0..4
+  const int mant = ((m - (1 << k)) << 3) >> k;  // 3 mantissa bits, exact for m <= 16
+  return sgn | (uint32_t)((k + 7) << 3) | (uint32_t)mant;
+}
+}  // namespace
+
+__global__ __launch_bounds__(256) void split_rows_fp8_kernel(const double* X, long long ldx, int rows, int rows_pad,
+                                                             int ncols, int ncols_pad, int ns, uint8_t* out,
+                                                             uint32_t* scales, double* norm2) {
+  const int lane = threadIdx.x & 63;
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int b = blockIdx.y;
+  if (row >= rows_pad) return;
+  const int nch = ncols_pad >> 6;
+  uint8_t* orow = out + ((size_t)b * rows_pad + row) * (size_t)ncols_pad * ns;
+  uint32_t* srow = scales + ((size_t)b * rows_pad + row) * (size_t)nch * 2;
+  const int h = (lane & 31) >> 4, e = (lane & 15) + 16 * (lane >> 5);
+  const double* x = X + ((size_t)b * rows + (row < rows ? row : 0)) * ldx;
+  double q = 0.0;
+  for (int ch = 0; ch < nch; ++ch) {
+    const int c = ch * 64 + lane;
+    const double v = (row < rows && c < ncols) ? x[c] : 0.0;
+    q += v * v;
+    double m = fabs(v);
+    for (int off = 16; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));  // within the 32-lane block
+    int E = 0;
+    if (m > 0.0) frexp(m, &E);
+    double r = (m > 0.0) ? ldexp(v, 4 - E) : 0.0;
+    uint32_t word = 0u;
+    for (int t = 0; t < ns; ++t) {
+      const double s = rint(r);
+      r = (r - s) * 32.0;
+      int sb = 127 + E - 4 - 5 * t;
+      int si = (int)s;
+      if (sb < 0) {  // scale not representable: drop this slice
+        sb = 0;
+        si = 0;
+      }
+      orow[((size_t)ch * ns + t) * 64 + 32 * h + e] = (uint8_t)e4m3_of_int(si);
+      word |= (uint32_t)sb << (8 * t);
+    }
+    if ((lane & 31) == 0) srow[ch * 2 + (lane >> 5)] = word;
+  }
+  q = wave_sum(q);
+  if (norm2 && lane == 0 && row < rows) norm2[(size_t)b * rows + row] = q;
+}
+
+hipError_t launch_split_rows_fp8(const double* X, long long ldx, int nb, int rows, int rows_pad, int ncols,
+                                 int ncols_pad, int ns, uint8_t* out, uint32_t* scales, double* norm2,
+                                 hipStream_t st) {
+  if (rows_pad <= 0 || nb <= 0) return hipSuccess;
+  if (ncols_pad % 64 != 0 || ns < 1 || ns > 4) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(split_rows_fp8_kernel, dim3((rows_pad + 3) / 4, nb), dim3(256), 0, st, X, ldx, rows, rows_pad,
+                     ncols, ncols_pad, ns, out, scales, norm2);
+  return hipGetLastError();
+}
+
 }  // namespace dfpt2
