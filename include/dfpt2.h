@@ -72,7 +72,9 @@ typedef struct dfpt2_opts {
   double  s;        /* DSRG flow parameter s (Eh^-2), > 0 */
   int32_t precision;          /* dfpt2_precision */
   int32_t slices_gemm1;       /* slices per operand of V = B B^T; 0 = precision default (BF16: 4, range 2..4) */
-  int32_t slices_gemm2;       /* slices per operand of the density product; 0 = default */
+  int32_t slices_gemm2;       /* slices per operand of the density product: 0 = precision default
+                               (BF16: 4; FP64, FP8: FP64 density), 1 = FP64 density, 2..4 = BF16
+                               slices (BF16 precision only) */
   int32_t density_convention; /* 0: spin-summed Gamma^(2)_vv (Eq. A9); 1: per spin (half) */
   int64_t pair_batch;         /* unordered pairs per batch; 0 = library default */
 } dfpt2_opts;
@@ -239,7 +241,8 @@ enum {
   DFPT2_STAGE_TRANSFORM = 6,  /* recanonicalization GEMMs and B transform */
   DFPT2_STAGE_KEPT_PAIR = 7,  /* pair kernel of the kept-space energy */
   DFPT2_STAGE_SCREEN = 8,     /* pair features, MLP, mask compaction */
-  DFPT2_NSTAGE = 9
+  DFPT2_STAGE_SPLIT_T = 9,    /* amplitude splitting into BF16 slices for the density */
+  DFPT2_NSTAGE = 10
 };
 int dfpt2_profile_enable(int on);
 int dfpt2_profile_read(double* ms, int64_t* launches);

@@ -79,7 +79,7 @@ SIGNATURES = {
     "dfpt2_profile_read": (_int, [ctypes.POINTER(_dbl), ctypes.POINTER(_i64)]),
 }
 
-STAGES = ["pair", "density", "split", "reduce", "active", "eigh", "transform", "kept_pair", "screen"]
+STAGES = ["pair", "density", "split", "reduce", "active", "eigh", "transform", "kept_pair", "screen", "split_t"]
 
 _lib = None
 

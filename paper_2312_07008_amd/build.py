@@ -29,6 +29,8 @@ SOURCES = [
     "split.hip",
     "pair_bf16.hip",
     "pair_fp8.hip",
+    "split_t.hip",
+    "density_bf16.hip",
     "active.hip",
     "screen.hip",
     "prof.cpp",

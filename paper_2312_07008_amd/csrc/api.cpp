@@ -85,9 +85,30 @@ int plan_pass(const dfpt2_opts* o, PassPlan* pl, bool energy_only) {
   p.precision = o->precision;
   p.ns1 = o->slices_gemm1 ? o->slices_gemm1 : default_slices_gemm1(o->precision);
   p.n_v_pad = (p.n_v + 63) / 64 * 64;
-  p.n_aux_pad = p.precision == DFPT2_FP8_SLICED ? (p.n_aux + 63) / 64 * 64 : (p.n_aux + 15) / 16 * 16;
+  p.n_aux_pad = p.precision == DFPT2_FP8_SLICED ? (p.n_aux + 63) / 64 * 64 : (p.n_aux + 31) / 32 * 32;
   if (p.precision != DFPT2_FP64 && (p.ns1 < 2 || p.ns1 > 4))
     return fail(DFPT2_ERR_INVALID_ARG, "slices_gemm1 must lie in [2, 4] for BF16 and FP8 slicing");
+  p.ns2 = o->slices_gemm2 ? o->slices_gemm2 : (p.precision == DFPT2_BF16_SLICED ? 4 : 1);
+  if (p.ns2 > 4 || (p.ns2 > 1 && p.precision != DFPT2_BF16_SLICED))
+    return fail(DFPT2_ERR_INVALID_ARG, "slices_gemm2 must be 1 (FP64 density) or, with BF16 precision, 2..4");
+  if (energy_only) p.ns2 = 1;
+  // split-BF16 density: splits of the pair range chosen so that tile pairs x splits
+  // fill whole rounds of two workgroups per CU on 256 CUs
+  p.nsplit2 = 1;
+  if (p.ns2 >= 2) {
+    double best = 1e30;
+    const int cap = p.batch < 64 ? p.batch : 64;
+    for (int k = 1; k <= cap; ++k) {
+      const double w = (double)p.nTP * k;
+      const double rounds = std::ceil(w / 512.0);
+      const double waste = (rounds * 512.0 - w) / w + (w < 2048.0 ? 1.0 : 0.0);
+      if (waste < best - 1e-12) {
+        best = waste;
+        p.nsplit2 = k;
+      }
+    }
+  }
+  p.nsplit_all = p.nsplit > p.nsplit2 ? p.nsplit : p.nsplit2;
 
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -102,12 +123,16 @@ int plan_pass(const dfpt2_opts* o, PassPlan* pl, bool energy_only) {
   p.off_tpart = take(sizeof(double) * (size_t)p.batch * p.nTP);
   p.off_pe = take(sizeof(double) * 2 * (size_t)(p.n_up > 0 ? p.n_up : 1));
   p.off_tn2 = take(sizeof(double) * (size_t)(p.n_up > 0 ? p.n_up : 1));
-  p.off_Dpart = take(energy_only ? 0 : sizeof(double) * mat * p.nsplit);
+  p.off_Dpart = take(energy_only ? 0 : sizeof(double) * mat * p.nsplit_all);
   const size_t slice_bytes = p.precision == DFPT2_BF16_SLICED ? sizeof(__bf16) : p.precision == DFPT2_FP8_SLICED ? 1 : 0;
   p.off_Bs = take(slice_bytes * p.ns1 * p.n_h * p.n_v_pad * p.n_aux_pad);
   p.off_scales = take(p.precision == DFPT2_FP8_SLICED ? sizeof(uint32_t) * 2 * (size_t)p.n_h * p.n_v_pad * (p.n_aux_pad / 64)
                                                       : 0);
   p.off_norm2 = take(p.precision != DFPT2_FP64 ? sizeof(double) * (size_t)p.n_h * p.n_v : 0);
+  p.off_Ts = take(p.ns2 >= 2 ? sizeof(__bf16) * 4 * (size_t)p.batch * p.n_v_pad * p.n_v_pad * p.ns2 : 0);
+  p.off_dg = take(p.ns2 >= 2 ? sizeof(double) * (size_t)p.batch * (p.n_v_pad / 64) * p.n_v_pad : 0);
+  p.off_tmax = take(p.ns2 >= 2 ? sizeof(unsigned long long) * 4 * (size_t)p.batch * p.n_v_pad : 0);
+  p.off_diag = take(p.ns2 >= 2 ? sizeof(double) * (size_t)p.n_v : 0);
   // active holes: stacked amplitude/integral matrices before and after the rotation
   p.n_ca = p.n_core * p.n_act;
   p.n_aa_un = p.n_act * (p.n_act + 1) / 2;
@@ -215,6 +240,8 @@ hipError_t launch_pair(const PairLaunch& L, const PairKernelArgs& a, int n_pairs
   b.Vr = a.Vr;
   b.epart = a.epart;
   b.tpart = a.tpart;
+  b.tmax = L.precision == DFPT2_BF16_SLICED ? a.tmax : nullptr;
+  b.dgp = b.tmax ? a.dgp : nullptr;
   b.n_v = a.n_v;
   b.n_v_pad = L.n_v_pad;
   b.n_aux_pad = L.n_aux_pad;
@@ -408,7 +435,9 @@ int run_pass(const PassPlan& pl, const dfpt2_opts& o, const double* eps_h, const
 
   if (!pl.energy_only) {
     ProfScope ps(DFPT2_STAGE_REDUCE, s);
-    if ((e = launch_fill(Dpart, mat * pl.nsplit, 0.0, s)) != hipSuccess) return hip_fail(e, "fill");
+    if ((e = launch_fill(Dpart, mat * pl.nsplit_all, 0.0, s)) != hipSuccess) return hip_fail(e, "fill");
+    if (pl.ns2 >= 2 && (e = launch_fill(reinterpret_cast<double*>(ws + pl.off_diag), pl.n_v, 0.0, s)) != hipSuccess)
+      return hip_fail(e, "fill");
   }
   const int stage_pair = pl.energy_only ? DFPT2_STAGE_KEPT_PAIR : DFPT2_STAGE_PAIR;
   PairKernelArgs pa{};
@@ -435,6 +464,13 @@ int run_pass(const PassPlan& pl, const dfpt2_opts& o, const double* eps_h, const
   for (int p0 = 0, b = 0; p0 < count; p0 += pl.batch, ++b) {
     const int np = (count - p0 < pl.batch) ? count - p0 : pl.batch;
     pa.pairs = pairs + p0;
+    if (pl.ns2 >= 2) {  // row maxima and diagonal partials for the split-BF16 density
+      pa.tmax = reinterpret_cast<unsigned long long*>(ws + pl.off_tmax);
+      pa.dgp = reinterpret_cast<double*>(ws + pl.off_dg);
+      ProfScope ps(DFPT2_STAGE_SPLIT_T, s);
+      if ((e = launch_fill(reinterpret_cast<double*>(pa.tmax), (size_t)np * 4 * pl.n_v_pad, 0.0, s)) != hipSuccess)
+        return hip_fail(e, "fill");
+    }
     {
       ProfScope ps(stage_pair, s);
       if ((e = launch_pair(L, pa, np, s)) != hipSuccess) return hip_fail(e, "pair kernel");
@@ -445,6 +481,31 @@ int run_pass(const PassPlan& pl, const dfpt2_opts& o, const double* eps_h, const
         return hip_fail(e, "pair reduce");
     }
     if (pl.energy_only) continue;
+    if (pl.ns2 >= 2) {
+      __bf16* Ts = reinterpret_cast<__bf16*>(ws + pl.off_Ts);
+      {
+        ProfScope ps(DFPT2_STAGE_SPLIT_T, s);
+        if ((e = launch_split_t_bf16(T, pairs + p0, nullptr, pl.w_density, np, pl.n_v, pl.n_v_pad, pl.ns2, pa.tmax,
+                                     pa.dgp, Ts, reinterpret_cast<double*>(ws + pl.off_diag), s)) != hipSuccess)
+          return hip_fail(e, "amplitude split");
+      }
+      DensitySlicedArgs ds{};
+      ds.Ts = Ts;
+      ds.pw = nullptr;
+      ds.pairs = pairs + p0;
+      ds.Dpart = Dpart;
+      ds.n_v = pl.n_v;
+      ds.n_v_pad = pl.n_v_pad;
+      ds.nt = pl.nt;
+      ds.nTP = pl.nTP;
+      ds.n_pairs = np;
+      ds.nsplit = pl.nsplit2 < np ? pl.nsplit2 : np;
+      ds.w = pl.w_density;
+      ds.accumulate = 1;
+      ProfScope ps(DFPT2_STAGE_DENSITY, s);
+      if ((e = launch_density_bf16(ds, pl.ns2, s)) != hipSuccess) return hip_fail(e, "density kernel (BF16)");
+      continue;
+    }
     da.pairs = pairs + p0;
     da.n_pairs = np;
     da.nsplit = pl.nsplit < np ? pl.nsplit : np;
@@ -462,7 +523,8 @@ int run_pass(const PassPlan& pl, const dfpt2_opts& o, const double* eps_h, const
   {
     ProfScope ps_tail(DFPT2_STAGE_REDUCE, s);
     if (!pl.energy_only) {
-      if ((e = launch_density_reduce(Dpart, pl.nsplit, pl.n_v, D, s)) != hipSuccess)
+      const double* diag = pl.ns2 >= 2 ? reinterpret_cast<const double*>(ws + pl.off_diag) : nullptr;
+      if ((e = launch_density_reduce(Dpart, pl.nsplit_all, pl.n_v, diag, D, s)) != hipSuccess)
         return hip_fail(e, "density reduce");
     }
     if ((e = launch_energy_finalize(pe, tn2, pairs, d_count, pl.n_up, pl.n_h, e_out, pair_energy, pair_tnorm,

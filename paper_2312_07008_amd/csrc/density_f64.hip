@@ -169,7 +169,7 @@ __global__ __launch_bounds__(256, 2) void density_f64_kernel(DensityKernelArgs a
     }
 }
 
-__global__ void density_reduce_kernel(const double* Dpart, int nsplit, int n_v, double* D) {
+__global__ void density_reduce_kernel(const double* Dpart, int nsplit, int n_v, const double* diag, double* D) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   const int a = blockIdx.y;
   if (b >= n_v || a > b) return;
@@ -177,6 +177,7 @@ __global__ void density_reduce_kernel(const double* Dpart, int nsplit, int n_v, 
   const size_t stride = (size_t)n_v * n_v;
   double v = 0.0;
   for (int s = 0; s < nsplit; ++s) v += Dpart[off + s * stride];
+  if (diag && a == b) v += diag[a];
   D[off] = v;
   D[(size_t)b * n_v + a] = v;
 }
@@ -191,9 +192,10 @@ hipError_t launch_density_f64(const DensityKernelArgs& a, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_density_reduce(const double* Dpart, int nsplit, int n_v, double* D, hipStream_t st) {
+hipError_t launch_density_reduce(const double* Dpart, int nsplit, int n_v, const double* diag, double* D,
+                                 hipStream_t st) {
   dim3 block(256), grid((n_v + 255) / 256, n_v);
-  hipLaunchKernelGGL(density_reduce_kernel, grid, block, 0, st, Dpart, nsplit, n_v, D);
+  hipLaunchKernelGGL(density_reduce_kernel, grid, block, 0, st, Dpart, nsplit, n_v, diag, D);
   return hipGetLastError();
 }
 

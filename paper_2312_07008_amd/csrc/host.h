@@ -21,13 +21,16 @@ struct PassPlan {
   int nt, nTP;      // 64-wide virtual tiles and upper-triangle tile pairs
   int n_up;         // unordered core-core pairs
   int batch;        // unordered pairs per batch
-  int nsplit;       // density split slices
+  int nsplit;       // density split slices (FP64 density kernel)
+  int nsplit2;      // density split slices (split-BF16 density kernel)
+  int nsplit_all;   // slices of Dpart: max(nsplit, nsplit2)
+  int ns2;          // slices per operand of the density product (1 = FP64 density)
   double w_density; // density weight of one ordered closed-shell pair
   int precision;    // dfpt2_precision
   bool energy_only; // no amplitudes stored, no density (kept-space energy)
   int ns1;          // slices per operand of the pair product (mixed precision)
   int n_v_pad, n_aux_pad;
-  size_t off_pairs, off_count, off_T, off_epart, off_tpart, off_pe, off_tn2, off_Dpart, off_Bs, off_scales, off_norm2;
+  size_t off_pairs, off_count, off_T, off_epart, off_tpart, off_pe, off_tn2, off_Dpart, off_Bs, off_scales, off_norm2, off_Ts, off_dg, off_tmax, off_diag;
   // active holes
   int n_ca, n_aa_un, cpb, act_cap;
   size_t off_act_T, off_act_V, off_act_Tr, off_act_Vr, off_act_pairs, off_act_slots, off_act_pairs2,

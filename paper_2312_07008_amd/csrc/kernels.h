@@ -14,6 +14,8 @@ struct PairKernelArgs {
   double* Vr;           // [n_pairs][n_v][n_v] renormalized integrals out, or null
   double* epart;        // [n_pairs][nTP] energy partial per tile pair, or null
   double* tpart;        // [n_pairs][nTP] ||T||^2 partial per tile pair, or null
+  unsigned long long* tmax;  // split-BF16 only, or null: row maxima for the density slices (PairSlicedArgs)
+  double* dgp;               // with tmax: diagonal partial sums
   int n_v, n_aux, nt, nTP;
   double s;
   double e_weight;      // energy weight of one ordered pair
@@ -33,6 +35,8 @@ struct PairSlicedArgs {
   double* Vr;           // [n_pairs][n_v][n_v] renormalized integrals out, or null
   double* epart;
   double* tpart;
+  unsigned long long* tmax;  // BF16 only, or null: [n_pairs][4][n_v_pad] row maxima for the density slices
+  double* dgp;               // with tmax: [n_pairs][nt][n_v_pad] diagonal partial sums (split_t.hip)
   int n_v, n_v_pad, n_aux_pad, nt, nTP;
   int n_blk_pairs;      // pairs of this launch (set by the launcher)
   double s;
@@ -59,7 +63,28 @@ struct DensityKernelArgs {
   int accumulate;       // add into Dpart instead of overwriting
 };
 hipError_t launch_density_f64(const DensityKernelArgs& a, hipStream_t st);
-hipError_t launch_density_reduce(const double* Dpart, int nsplit, int n_v, double* D, hipStream_t st);
+
+// split-BF16 density: amplitude slices (split_t.hip) and the sliced product
+struct DensitySlicedArgs {
+  const __bf16* Ts;     // [n_pairs][4][n_v_pad][n_v_pad/16][ns][16] (split_t.hip)
+  const double* pw;     // [n_pairs] per-pair weight, or null
+  const int2* pairs;    // [n_pairs]
+  double* Dpart;        // [nsplit][n_v][n_v]
+  int n_v, n_v_pad, nt, nTP, n_pairs, nsplit;
+  double w;             // weight of one ordered pair
+  int accumulate;
+};
+// slices of the four density operands of every pair of a batch (T: [n_pairs][n_v][n_v]),
+// from the row maxima tmax ([n_pairs][4][n_v_pad]) the pair kernel recorded, plus
+// diag[a] += the exact FP64 diagonal of the batch's contribution from the pair
+// kernel's partial sums dgp ([n_pairs][n_v_pad/64][n_v_pad])
+hipError_t launch_split_t_bf16(const double* T, const int2* pairs, const double* pw, double w, int n_pairs, int n_v,
+                               int n_v_pad, int ns, const unsigned long long* tmax, const double* dgp, __bf16* out,
+                               double* diag, hipStream_t st);
+hipError_t launch_density_bf16(const DensitySlicedArgs& a, int ns, hipStream_t st);
+// D = sum of the split slices (+ diag on the diagonal if non-null), both triangles
+hipError_t launch_density_reduce(const double* Dpart, int nsplit, int n_v, const double* diag, double* D,
+                                 hipStream_t st);
 
 // ------------------------------------------------------------ small kernels
 hipError_t launch_fill(double* p, size_t n, double v, hipStream_t st);

@@ -1,0 +1,154 @@
+// Amplitude splitting for the split-BF16 density product (row a4 of the pass).
+//
+// For one unordered pair {i <= j} with amplitude matrix T = T^{ij} (n_v x n_v),
+// the two ordered pairs contribute X1 Y1^T + X2 Y2^T to D (Eq. A9 with zero
+// cumulants, see density_f64.hip), with, for a virtual c along the contraction,
+//     m = 0:  X1[a][c] = T[a][c]
+//     m = 1:  X2[a][c] = T[c][a]
+//     m = 2:  Y1[b][c] = 2 T[b][c] - T[c][b]
+//     m = 3:  Y2[b][c] = 2 T[c][b] - T[b][c]
+// Every row of the four matrices is split like a row of B (split.hip): scale
+// 2^E from the row's largest magnitude, ns true-scale BF16 slices whose integer
+// digits s_t (|s_t| <= 256) satisfy sum_t s_t 512^(ns-t) = rint(x 2^(8 + 9(ns-1) - E)),
+// so the density kernel can sum the slice products of one pair exactly in FP32.
+// The digits are taken from that rounded integer with balanced base-512 digit
+// extraction, which gives the same represented value as slicing by successive
+// round-to-nearest steps.  Output per pair q: [q][m][n_v_pad][n_v_pad/16][ns][16]
+// (rows and columns >= n_v are zeros), the chunk-interleaved layout of B's slices.
+//
+// The diagonal of the pair's contribution, w_q sum_c (X1 Y1 + X2 Y2)[a][c] =
+// w_q sum_c 2 (x^2 - x y + y^2) with x = T[a][c], y = T[c][a], is summed here in
+// FP64: on the diagonal the rows of X and Y carry the same amplitudes, so the
+// slice products the density kernel drops would not average out there, and the
+// diagonal carries the trace of D.  The density kernel leaves the diagonal out.
+//
+// The four row maxima and the diagonal partial sums come from the pair kernel's
+// epilogue (pair_bf16.hip), which holds every amplitude once.  Here one kernel
+// writes the slices and one workgroup per virtual a then sums the diagonal
+// partials in a fixed order.
+#include <cmath>
+
+#include "common.h"
+#include "kernels.h"
+
+namespace dfpt2 {
+
+namespace {
+constexpr int TB = 64;
+constexpr int LD = TB + 1;
+typedef uint32_t u4 __attribute__((ext_vector_type(4)));
+}  // namespace
+
+// ---------------------------------------------------------------- slices
+// Workgroup = (row block A, column block C, pair q): rows A x columns C of the
+// four matrices.  x = T[a][c] comes straight from global memory (thread = row,
+// 16-column quarter: 128 contiguous bytes), y = T[c][a] from the mirror tile
+// T[C, A] staged in LDS.  Each matrix's slices go through an LDS staging area
+// laid out like the output rows (64 rows x 512 bytes for 4 slices, one 16-byte
+// pad per row against bank conflicts), then out with lane-contiguous stores.
+template <int NS>
+__global__ __launch_bounds__(256) void split_t_bf16_kernel(const double* T, int n_v, int n_v_pad, int nt,
+                                                           const unsigned long long* tmax, __bf16* out) {
+  constexpr int RU4 = 4 * NS * 2;  // u4 per output row segment (64 columns)
+  constexpr int SLD = RU4 + 1;     // padded staging row
+  __shared__ double tm[TB][LD];    // T[C-block row][A-block col]
+  __shared__ u4 stage[TB * SLD];
+  const int A = blockIdx.x / nt, C = blockIdx.x - (blockIdx.x / nt) * nt, q = blockIdx.y;
+  const double* Tp = T + (size_t)q * n_v * n_v;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < TB * TB; e += 256) {
+    const int r = e >> 6, c = e & 63;
+    const int hr = C * TB + r, hc = A * TB + c;
+    tm[r][c] = (hr < n_v && hc < n_v) ? Tp[(size_t)hr * n_v + hc] : 0.0;
+  }
+  const int r = tid >> 2, k4 = tid & 3;
+  const int row = A * TB + r;
+  double x[16];
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    const int gc = C * TB + k4 * 16 + j;
+    x[j] = (row < n_v && gc < n_v) ? Tp[(size_t)row * n_v + gc] : 0.0;
+  }
+  __syncthreads();
+  double y[16];
+#pragma unroll
+  for (int j = 0; j < 16; ++j) y[j] = tm[k4 * 16 + j][r];
+
+  const size_t row_elems = (size_t)n_v_pad * NS;
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    const double mx = __longlong_as_double((long long)tmax[((size_t)q * 4 + m) * n_v_pad + row]);
+    int E = 0;
+    if (mx > 0.0) frexp(mx, &E);
+    bf8v sl[NS][2];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      const double v = m == 0 ? x[j] : m == 1 ? y[j] : m == 2 ? 2.0 * x[j] - y[j] : 2.0 * y[j] - x[j];
+      long long Z = (mx > 0.0) ? (long long)rint(ldexp(v, 8 + 9 * (NS - 1) - E)) : 0;
+#pragma unroll
+      for (int t = NS - 1; t >= 0; --t) {
+        const int d = t ? (int)(((Z + 256) & 511) - 256) : (int)Z;
+        Z = (Z - d) >> 9;
+        sl[t][j >> 3][j & 7] = (__bf16)ldexpf((float)d, E - 8 - 9 * t);
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < NS; ++t) {
+      stage[r * SLD + k4 * (2 * NS) + 2 * t] = __builtin_bit_cast(u4, sl[t][0]);
+      stage[r * SLD + k4 * (2 * NS) + 2 * t + 1] = __builtin_bit_cast(u4, sl[t][1]);
+    }
+    __syncthreads();
+    __bf16* dst = out + ((size_t)q * 4 + m) * n_v_pad * row_elems + (size_t)C * (4 * NS * 16);
+    for (int f = tid; f < TB * RU4; f += 256) {
+      const int rr = f / RU4, pc = f - rr * RU4;
+      reinterpret_cast<u4*>(dst + (size_t)(A * TB + rr) * row_elems)[pc] = stage[rr * SLD + pc];
+    }
+    __syncthreads();
+  }
+}
+
+// diag[a] += sum over pairs q and column blocks of w_q dgp[q][blk][a], in a fixed
+// order (strided per thread, then a fixed tree), so the result is reproducible
+__global__ __launch_bounds__(256) void diag_accumulate_kernel(const double* dgp, const int2* pairs, const double* pw,
+                                                              double w, int n_pairs, int nt, int n_v_pad,
+                                                              double* diag) {
+  __shared__ double red[256];
+  const int a = blockIdx.x, t = threadIdx.x;
+  double v = 0.0;
+  for (int i = t; i < n_pairs * nt; i += 256) {
+    const int q = i / nt;
+    const int2 pr = pairs[q];
+    double wq = w * (pr.x == pr.y ? 0.5 : 1.0);
+    if (pw) wq *= pw[q];
+    v += wq * dgp[(size_t)i * n_v_pad + a];
+  }
+  red[t] = v;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (t < h) red[t] += red[t + h];
+    __syncthreads();
+  }
+  if (t == 0) diag[a] += red[0];
+}
+
+hipError_t launch_split_t_bf16(const double* T, const int2* pairs, const double* pw, double w, int n_pairs, int n_v,
+                               int n_v_pad, int ns, const unsigned long long* tmax, const double* dgp, __bf16* out,
+                               double* diag, hipStream_t st) {
+  if (n_pairs <= 0) return hipSuccess;
+  if (n_v_pad % TB != 0 || n_v_pad < n_v) return hipErrorInvalidValue;
+  const int nt = n_v_pad / TB;
+  hipError_t e;
+  dim3 grid(nt * nt, n_pairs), block(256);
+  switch (ns) {
+    case 2: hipLaunchKernelGGL(split_t_bf16_kernel<2>, grid, block, 0, st, T, n_v, n_v_pad, nt, tmax, out); break;
+    case 3: hipLaunchKernelGGL(split_t_bf16_kernel<3>, grid, block, 0, st, T, n_v, n_v_pad, nt, tmax, out); break;
+    case 4: hipLaunchKernelGGL(split_t_bf16_kernel<4>, grid, block, 0, st, T, n_v, n_v_pad, nt, tmax, out); break;
+    default: return hipErrorInvalidValue;
+  }
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(diag_accumulate_kernel, dim3(n_v), dim3(256), 0, st, dgp, pairs, pw, w, n_pairs, nt, n_v_pad,
+                     diag);
+  return hipGetLastError();
+}
+
+}  // namespace dfpt2

@@ -46,12 +46,17 @@ def test_workspace_sizes(lib):
     assert 0 < n1 < n3
     assert dp.fno_truncate_workspace_size(60) > 0
     assert dp.pt2_correction_workspace_size(dp.make_opts(10, 0, 60, 200, 0.5), 40) > 0
+    # the split-BF16 density keeps BF16 slices of four matrices per pair of a batch
+    b_fp64_d = dp.workspace_size(dp.make_opts(80, 0, 1200, 4000, 0.5, precision=1, slices_gemm2=1))
+    b_bf16_d = dp.workspace_size(dp.make_opts(80, 0, 1200, 4000, 0.5, precision=1))
+    assert b_bf16_d - b_fp64_d >= 4 * 4 * 2 * 512 * 1216 * 1216
 
 
 @pytest.mark.parametrize("bad", [dict(s=0.0), dict(s=-1.0), dict(s=float("nan")), dict(n_vir=0),
                                  dict(n_aux=0), dict(n_core=0, n_act=0), dict(n_core=-1),
                                  dict(precision=7), dict(density_convention=3), dict(slices_gemm1=9),
-                                 dict(pair_batch=-5)])
+                                 dict(pair_batch=-5), dict(slices_gemm2=3), dict(precision=1, slices_gemm2=5),
+                                 dict(precision=1, slices_gemm1=5), dict(precision=2, slices_gemm2=2)])
 def test_invalid_options_rejected(lib, bad):
     kw = dict(n_core=10, n_act=0, n_vir=60, n_aux=200, s=0.5)
     kw.update({k: v for k, v in bad.items() if k in kw})

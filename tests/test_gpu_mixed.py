@@ -65,3 +65,36 @@ def test_bf16_truncation_and_correction_c1():
                                  t["n_kept"], g["raw"]["e_pt2"])
     cc = c["correction"].cpu().numpy()
     assert dd_diff((cc[0], cc[1]), ref["correction"]) <= E_TOL_MIXED
+
+
+def test_bf16_density_slices():
+    """Split-BF16 density product (default, 4 slices) against the FP64 density kernel
+    on the same BF16 amplitudes and against the oracle; the error of D falls with the
+    density slice count (about 2^-(9k-1) relative for k slices)."""
+    inp = synth.generate(9, 0, 150, 200, seed=5)
+    ref = o.pt2_pass_inputs(inp, 0.5)
+    scale = np.abs(ref.D_vv).max()
+    g64 = gpu_pass(inp, 0.5, precision=BF16, slices_gemm2=1)
+    errs = []
+    for k in (2, 3, 4):
+        g = gpu_pass(inp, 0.5, precision=BF16, slices_gemm2=k)
+        assert g["energy"] == g64["energy"]            # the energy does not involve the density product
+        assert np.array_equal(g["D"], g["D"].T)
+        errs.append(np.abs(g["D"] - ref.D_vv).max() / scale)
+    print("relative D errors by density slice count:", errs,
+          "FP64 density:", np.abs(g64["D"] - ref.D_vv).max() / scale, flush=True)
+    assert errs[0] > errs[1] > errs[2]
+    for k, e in zip((2, 3, 4), errs):
+        assert e <= 16.0 * 2.0 ** -(9 * k - 1) + 1e-11
+    assert np.abs(g["D"] - g64["D"]).max() <= 1e-10 * scale
+
+
+def test_bf16_density_reproducible_and_batched():
+    """Fixed-order split reduction: repeated runs are bitwise equal, and batching the
+    pairs differently changes D only at the rounding level."""
+    inp = synth.generate(11, 0, 130, 96, seed=8)
+    a = gpu_pass(inp, 0.5, precision=BF16)
+    b = gpu_pass(inp, 0.5, precision=BF16)
+    assert np.array_equal(a["D"], b["D"]) and a["energy"] == b["energy"]
+    c = gpu_pass(inp, 0.5, precision=BF16, pair_batch=7)
+    assert np.abs(c["D"] - a["D"]).max() <= 1e-12 * np.abs(a["D"]).max()
