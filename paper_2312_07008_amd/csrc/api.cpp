@@ -84,7 +84,9 @@ int plan_pass(const dfpt2_opts* o, PassPlan* pl, bool energy_only) {
   p.energy_only = energy_only;
   p.precision = o->precision;
   p.ns1 = o->slices_gemm1 ? o->slices_gemm1 : default_slices_gemm1(o->precision);
-  p.n_v_pad = (p.n_v + 63) / 64 * 64;
+  p.n_v_pad_d = (p.n_v + 63) / 64 * 64;
+  p.n_v_pad = p.n_v_pad_d;  // slab rows of the sliced operands
+  p.nTP1 = p.nTP;
   p.n_aux_pad = p.precision == DFPT2_FP8_SLICED ? (p.n_aux + 63) / 64 * 64 : (p.n_aux + 31) / 32 * 32;
   if (p.precision != DFPT2_FP64 && (p.ns1 < 2 || p.ns1 > 4))
     return fail(DFPT2_ERR_INVALID_ARG, "slices_gemm1 must lie in [2, 4] for BF16 and FP8 slicing");
@@ -119,8 +121,8 @@ int plan_pass(const dfpt2_opts* o, PassPlan* pl, bool energy_only) {
   p.off_pairs = take(sizeof(int2) * (size_t)(p.n_up > 0 ? p.n_up : 1));
   p.off_count = take(sizeof(int) * 4);
   p.off_T = take(energy_only ? 0 : sizeof(double) * mat * p.batch);
-  p.off_epart = take(sizeof(double) * (size_t)p.batch * p.nTP);
-  p.off_tpart = take(sizeof(double) * (size_t)p.batch * p.nTP);
+  p.off_epart = take(sizeof(double) * (size_t)p.batch * p.nTP1);
+  p.off_tpart = take(sizeof(double) * (size_t)p.batch * p.nTP1);
   p.off_pe = take(sizeof(double) * 2 * (size_t)(p.n_up > 0 ? p.n_up : 1));
   p.off_tn2 = take(sizeof(double) * (size_t)(p.n_up > 0 ? p.n_up : 1));
   p.off_Dpart = take(energy_only ? 0 : sizeof(double) * mat * p.nsplit_all);
@@ -129,9 +131,9 @@ int plan_pass(const dfpt2_opts* o, PassPlan* pl, bool energy_only) {
   p.off_scales = take(p.precision == DFPT2_FP8_SLICED ? sizeof(uint32_t) * 2 * (size_t)p.n_h * p.n_v_pad * (p.n_aux_pad / 64)
                                                       : 0);
   p.off_norm2 = take(p.precision != DFPT2_FP64 ? sizeof(double) * (size_t)p.n_h * p.n_v : 0);
-  p.off_Ts = take(p.ns2 >= 2 ? sizeof(__bf16) * 4 * (size_t)p.batch * p.n_v_pad * p.n_v_pad * p.ns2 : 0);
-  p.off_dg = take(p.ns2 >= 2 ? sizeof(double) * (size_t)p.batch * (p.n_v_pad / 64) * p.n_v_pad : 0);
-  p.off_tmax = take(p.ns2 >= 2 ? sizeof(unsigned long long) * 4 * (size_t)p.batch * p.n_v_pad : 0);
+  p.off_Ts = take(p.ns2 >= 2 ? sizeof(__bf16) * 4 * (size_t)p.batch * p.n_v_pad_d * p.n_v_pad_d * p.ns2 : 0);
+  p.off_dg = take(p.ns2 >= 2 ? sizeof(double) * (size_t)p.batch * (p.n_v_pad_d / 64) * p.n_v_pad_d : 0);
+  p.off_tmax = take(p.ns2 >= 2 ? sizeof(unsigned long long) * 4 * (size_t)p.batch * p.n_v_pad_d : 0);
   p.off_diag = take(p.ns2 >= 2 ? sizeof(double) * (size_t)p.n_v : 0);
   // active holes: stacked amplitude/integral matrices before and after the rotation
   p.n_ca = p.n_core * p.n_act;
@@ -155,7 +157,7 @@ int plan_pass(const dfpt2_opts* o, PassPlan* pl, bool energy_only) {
     p.off_act_slots2 = take(sizeof(int) * ac);
     p.off_act_wd = take(sizeof(double) * ac);
     p.off_act_we = take(sizeof(double) * ac);
-    p.off_act_tpart = take(sizeof(double) * ac * p.nTP);
+    p.off_act_tpart = take(sizeof(double) * ac * p.nTP1);
     p.off_act_tn2 = take(sizeof(double) * ac);
     p.off_act_epart = take(sizeof(double) * ac * (size_t)p.nt * p.nt);
     p.off_act_pe = take(sizeof(double) * 2 * (size_t)(p.n_ca + p.n_aa_un));
@@ -247,6 +249,7 @@ hipError_t launch_pair(const PairLaunch& L, const PairKernelArgs& a, int n_pairs
   b.n_aux_pad = L.n_aux_pad;
   b.nt = a.nt;
   b.nTP = a.nTP;
+  b.n_v_pad_d = (a.n_v + 63) / 64 * 64;
   b.s = a.s;
   b.e_weight = a.e_weight;
   return L.precision == DFPT2_FP8_SLICED ? launch_pair_gemm_fp8(b, L.ns, n_pairs, st)
@@ -294,7 +297,7 @@ static int run_active_blocks(const PassPlan& pl, const dfpt2_opts& o, const doub
   pa.n_v = nv;
   pa.n_aux = pl.n_aux;
   pa.nt = pl.nt;
-  pa.nTP = pl.nTP;
+  pa.nTP = pl.nTP1;
   pa.s = o.s;
   pa.e_weight = 1.0;
   pa.T = Tin;
@@ -321,7 +324,7 @@ static int run_active_blocks(const PassPlan& pl, const dfpt2_opts& o, const doub
     if ((e = launch_build_active_pairs(0, m0, nc, pl.n_core, na, pairs, slots, s)) != hipSuccess)
       return hip_fail(e, "active pairs");
     if ((e = launch_pair(L, pa, np, s)) != hipSuccess) return hip_fail(e, "pair kernel (core-active)");
-    if ((e = launch_pair_reduce(nullptr, tpart, pl.nTP, np, nullptr, tn2, s)) != hipSuccess)
+    if ((e = launch_pair_reduce(nullptr, tpart, pl.nTP1, np, nullptr, tn2, s)) != hipSuccess)
       return hip_fail(e, "pair reduce");
     if ((e = launch_scatter_active_pair_info(pairs, tn2, np, pl.n_h, pair_energy, pair_tnorm, s)) != hipSuccess)
       return hip_fail(e, "scatter");
@@ -351,7 +354,7 @@ static int run_active_blocks(const PassPlan& pl, const dfpt2_opts& o, const doub
     if ((e = launch_build_active_pairs(1, 0, 0, pl.n_core, na, pairs, slots, s)) != hipSuccess)
       return hip_fail(e, "active pairs");
     if ((e = launch_pair(L, pa, np, s)) != hipSuccess) return hip_fail(e, "pair kernel (active-active)");
-    if ((e = launch_pair_reduce(nullptr, tpart, pl.nTP, np, nullptr, tn2, s)) != hipSuccess)
+    if ((e = launch_pair_reduce(nullptr, tpart, pl.nTP1, np, nullptr, tn2, s)) != hipSuccess)
       return hip_fail(e, "pair reduce");
     if ((e = launch_scatter_active_pair_info(pairs, tn2, np, pl.n_h, pair_energy, pair_tnorm, s)) != hipSuccess)
       return hip_fail(e, "scatter");
@@ -447,7 +450,7 @@ int run_pass(const PassPlan& pl, const dfpt2_opts& o, const double* eps_h, const
   pa.n_v = pl.n_v;
   pa.n_aux = pl.n_aux;
   pa.nt = pl.nt;
-  pa.nTP = pl.nTP;
+  pa.nTP = pl.nTP1;
   pa.s = o.s;
   pa.e_weight = 1.0;  // 1/4 gamma_ii gamma_jj with gamma = 2 for core holes
   pa.T = pl.energy_only ? nullptr : T;
@@ -468,7 +471,7 @@ int run_pass(const PassPlan& pl, const dfpt2_opts& o, const double* eps_h, const
       pa.tmax = reinterpret_cast<unsigned long long*>(ws + pl.off_tmax);
       pa.dgp = reinterpret_cast<double*>(ws + pl.off_dg);
       ProfScope ps(DFPT2_STAGE_SPLIT_T, s);
-      if ((e = launch_fill(reinterpret_cast<double*>(pa.tmax), (size_t)np * 4 * pl.n_v_pad, 0.0, s)) != hipSuccess)
+      if ((e = launch_fill(reinterpret_cast<double*>(pa.tmax), (size_t)np * 4 * pl.n_v_pad_d, 0.0, s)) != hipSuccess)
         return hip_fail(e, "fill");
     }
     {
@@ -477,7 +480,7 @@ int run_pass(const PassPlan& pl, const dfpt2_opts& o, const double* eps_h, const
     }
     {
       ProfScope ps(DFPT2_STAGE_REDUCE, s);
-      if ((e = launch_pair_reduce(epart, tpart, pl.nTP, np, pe + 2 * (size_t)p0, tn2 + p0, s)) != hipSuccess)
+      if ((e = launch_pair_reduce(epart, tpart, pl.nTP1, np, pe + 2 * (size_t)p0, tn2 + p0, s)) != hipSuccess)
         return hip_fail(e, "pair reduce");
     }
     if (pl.energy_only) continue;
@@ -485,7 +488,7 @@ int run_pass(const PassPlan& pl, const dfpt2_opts& o, const double* eps_h, const
       __bf16* Ts = reinterpret_cast<__bf16*>(ws + pl.off_Ts);
       {
         ProfScope ps(DFPT2_STAGE_SPLIT_T, s);
-        if ((e = launch_split_t_bf16(T, pairs + p0, nullptr, pl.w_density, np, pl.n_v, pl.n_v_pad, pl.ns2, pa.tmax,
+        if ((e = launch_split_t_bf16(T, pairs + p0, nullptr, pl.w_density, np, pl.n_v, pl.n_v_pad_d, pl.ns2, pa.tmax,
                                      pa.dgp, Ts, reinterpret_cast<double*>(ws + pl.off_diag), s)) != hipSuccess)
           return hip_fail(e, "amplitude split");
       }
@@ -495,7 +498,7 @@ int run_pass(const PassPlan& pl, const dfpt2_opts& o, const double* eps_h, const
       ds.pairs = pairs + p0;
       ds.Dpart = Dpart;
       ds.n_v = pl.n_v;
-      ds.n_v_pad = pl.n_v_pad;
+      ds.n_v_pad = pl.n_v_pad_d;
       ds.nt = pl.nt;
       ds.nTP = pl.nTP;
       ds.n_pairs = np;

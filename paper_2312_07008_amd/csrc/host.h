@@ -19,6 +19,7 @@ size_t align_up(size_t x, size_t a);
 struct PassPlan {
   int n_core, n_act, n_h, n_v, n_aux;
   int nt, nTP;      // 64-wide virtual tiles and upper-triangle tile pairs
+  int nTP1;         // pair-kernel workgroup tiles per pair (energy partials per pair)
   int n_up;         // unordered core-core pairs
   int batch;        // unordered pairs per batch
   int nsplit;       // density split slices (FP64 density kernel)
@@ -29,7 +30,8 @@ struct PassPlan {
   int precision;    // dfpt2_precision
   bool energy_only; // no amplitudes stored, no density (kept-space energy)
   int ns1;          // slices per operand of the pair product (mixed precision)
-  int n_v_pad, n_aux_pad;
+  int n_v_pad, n_aux_pad;  // slab rows and columns of the sliced operands
+  int n_v_pad_d;           // 64-multiple of n_v: layout of the density slices and row data
   size_t off_pairs, off_count, off_T, off_epart, off_tpart, off_pe, off_tn2, off_Dpart, off_Bs, off_scales, off_norm2, off_Ts, off_dg, off_tmax, off_diag;
   // active holes
   int n_ca, n_aa_un, cpb, act_cap;

@@ -37,7 +37,9 @@ struct PairSlicedArgs {
   double* tpart;
   unsigned long long* tmax;  // BF16 only, or null: [n_pairs][4][n_v_pad] row maxima for the density slices
   double* dgp;               // with tmax: [n_pairs][nt][n_v_pad] diagonal partial sums (split_t.hip)
-  int n_v, n_v_pad, n_aux_pad, nt, nTP;
+  int n_v, n_v_pad, n_aux_pad, nt, nTP;  // n_v_pad: slab rows of Bs; nt: 64-wide tiles of n_v;
+                                        // nTP: workgroup tiles per pair
+  int n_v_pad_d;        // row stride of tmax / dgp (64-multiple)
   int n_blk_pairs;      // pairs of this launch (set by the launcher)
   double s;
   double e_weight;

@@ -128,9 +128,9 @@ __device__ inline void density_row_info(const PairSlicedArgs& a, int p, int I, i
       const int row = I * 64 + rw * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
       if (row < a.n_v) {
         if (m < 4)
-          atomicMax(a.tmax + ((size_t)p * 4 + m) * a.n_v_pad + row, (unsigned long long)__double_as_longlong(val));
+          atomicMax(a.tmax + ((size_t)p * 4 + m) * a.n_v_pad_d + row, (unsigned long long)__double_as_longlong(val));
         else
-          a.dgp[((size_t)p * a.nt + J) * a.n_v_pad + row] = val;
+          a.dgp[((size_t)p * a.nt + J) * a.n_v_pad_d + row] = val;
       }
     } else if (tid < 128 && I < J) {  // rows of J: waves (0, wc) and (1, wc), roles of x and y swapped
       const int cw = (tid - 64) >> 5, c = tid & 31;
@@ -140,9 +140,9 @@ __device__ inline void density_row_info(const PairSlicedArgs& a, int p, int I, i
       if (row < a.n_v) {
         if (m < 4) {
           const int mm = m ^ 1;  // |x| <-> |y|, |2x - y| <-> |2y - x|
-          atomicMax(a.tmax + ((size_t)p * 4 + mm) * a.n_v_pad + row, (unsigned long long)__double_as_longlong(val));
+          atomicMax(a.tmax + ((size_t)p * 4 + mm) * a.n_v_pad_d + row, (unsigned long long)__double_as_longlong(val));
         } else {
-          a.dgp[((size_t)p * a.nt + I) * a.n_v_pad + row] = val;
+          a.dgp[((size_t)p * a.nt + I) * a.n_v_pad_d + row] = val;
         }
       }
     }
