@@ -12,5 +12,7 @@ Modules:
   screening  pair features and rigorous bounds, the FP64 multilayer perceptron,
              its gradient, mean squared error and Adam, used to check the learned
              pair screen (which is not part of the paper's method)
+  naf        natural auxiliary functions (compression of the auxiliary basis
+             proposed in the paper's conclusions)
 """
-from . import dsrg_pt2, screening  # noqa: F401
+from . import dsrg_pt2, naf, screening  # noqa: F401
