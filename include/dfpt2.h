@@ -139,6 +139,53 @@ int fno_truncate(const double* D_vv, int64_t n_vir, double p_o, double degen_rel
                  double* occ, double* no_vecs, int64_t* n_kept, double* margins,
                  void* workspace, size_t ws_bytes, dfpt2_stream_t stream);
 
+/* Truncation rules for fno_truncate_rule. */
+typedef enum {
+  DFPT2_TRUNC_CUMULATIVE = 0, /* param = p_o in (0, 1]: smallest N' whose cumulative occupation
+                                 reaches p_o of the total (Eq. 10); the rule of fno_truncate */
+  DFPT2_TRUNC_FRACTION = 1,   /* param = p_v in (0, 1]: N' = ceil(p_v n_vir), a fixed fraction of
+                                 the virtuals (Eq. 9) */
+  DFPT2_TRUNC_CUTOFF = 2,     /* param = n_kappa: keep every NO whose occupation is >= n_kappa
+                                 (the occupation cutoff of Sec. 2); N' may be 0 */
+  DFPT2_TRUNC_FIXED = 3       /* param = N', an integer in [1, n_vir]: the same N' at every
+                                 geometry of a scan (Sec. 2 on the PES discontinuity) */
+} dfpt2_trunc_rule;
+
+/*
+ * Natural orbitals and truncation by any rule of dfpt2_trunc_rule, then the same
+ * optional near-degeneracy widening as fno_truncate.  Arguments as for
+ * fno_truncate, plus rule and param.  margins (host out [2] or NULL): for the
+ * cumulative rule as in fno_truncate; for the cutoff rule (n[N'-1] - n_kappa,
+ * n_kappa - n[N']); for the other rules the occupations either side of the cut
+ * (n[N'-1], n[N']); +inf where a neighbour does not exist.
+ * Errors: INVALID_ARG (unknown rule or parameter out of range), WORKSPACE, HIP,
+ * NOT_CONVERGED, NONFINITE.
+ */
+int fno_truncate_rule(const double* D_vv, int64_t n_vir, int rule, double param, double degen_rel_tol,
+                      double* occ, double* no_vecs, int64_t* n_kept, double* margins,
+                      void* workspace, size_t ws_bytes, dfpt2_stream_t stream);
+
+/* Workspace (bytes) for naf_compress (sizes from opts).  bytes: host out. */
+int naf_compress_workspace_size(const dfpt2_opts* opts, size_t* bytes);
+
+/*
+ * Natural auxiliary functions (the auxiliary-basis compression the paper's
+ * conclusions propose for this pass; Kallay's NAFs): with J[(i,a), P] = B^P_ia,
+ * W = J^T J = U diag(sigma) U^T, keep the n_naf functions with sigma_k > eps
+ * (eps <= 0 keeps all: then V = B B^T is reproduced to rounding) and form
+ * B~^k_ia = sum_P B^P_ia U_Pk.
+ *   opts    sizes only (n_core + n_act holes, n_vir, n_aux <= 16384)
+ *   B       [n_h][n_vir][n_aux] as for dfpt2_build_vv_density
+ *   B_naf   [n_h][n_vir][n_aux] capacity, out [n_h][n_vir][n_naf]: pass it with
+ *           n_aux = n_naf to dfpt2_build_vv_density / pt2_energy_correction
+ *   sigma   [n_aux] out, eigenvalues of W, descending
+ *   n_naf   host out
+ * Synchronizes the stream.  Errors: INVALID_ARG (also when eps removes every
+ * function), WORKSPACE, HIP, NOT_CONVERGED, NONFINITE.
+ */
+int naf_compress(const dfpt2_opts* opts, const double* B, double eps, double* B_naf, double* sigma,
+                 int64_t* n_naf, void* workspace, size_t ws_bytes, dfpt2_stream_t stream);
+
 /* Symmetric FP64 eigensolver used by fno_truncate (Eq. 8) and the
  * recanonicalization: A [n*n] symmetric (not modified); w [n] out ascending;
  * Z [n*n] out, column k is the eigenvector of w[k]. */

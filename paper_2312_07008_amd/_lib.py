@@ -18,6 +18,7 @@ ERR_UNSUPPORTED = -6
 FP64 = 0
 BF16_SLICED = 1
 FP8_SLICED = 2
+TRUNC_CUMULATIVE, TRUNC_FRACTION, TRUNC_CUTOFF, TRUNC_FIXED = 0, 1, 2, 3
 
 
 class DfptError(RuntimeError):
@@ -58,7 +59,11 @@ SIGNATURES = {
     "fno_truncate_workspace_size": (_int, [_i64, ctypes.POINTER(_sz)]),
     "fno_truncate": (_int, [_vp, _i64, _dbl, _dbl, _vp, _vp, ctypes.POINTER(_i64),
                             ctypes.POINTER(_dbl), _vp, _sz, _vp]),
+    "fno_truncate_rule": (_int, [_vp, _i64, _int, _dbl, _dbl, _vp, _vp, ctypes.POINTER(_i64),
+                                 ctypes.POINTER(_dbl), _vp, _sz, _vp]),
     "dfpt2_eigh_sym": (_int, [_vp, _i64, _vp, _vp, _vp, _sz, _vp]),
+    "naf_compress_workspace_size": (_int, [ctypes.POINTER(Opts), ctypes.POINTER(_sz)]),
+    "naf_compress": (_int, [ctypes.POINTER(Opts), _vp, _dbl, _vp, _vp, ctypes.POINTER(_i64), _vp, _sz, _vp]),
     "pt2_correction_workspace_size": (_int, [ctypes.POINTER(Opts), _i64, ctypes.POINTER(_sz)]),
     "pt2_energy_correction": (_int, [ctypes.POINTER(Opts), _vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp,
                                      _vp, _sz, _vp]),

@@ -16,7 +16,7 @@ from . import _lib
 from ._lib import Opts, check
 
 __all__ = ["make_opts", "workspace_size", "build_vv_density", "fno_truncate_workspace_size",
-           "fno_truncate", "eigh_sym", "pt2_correction_workspace_size", "pt2_energy_correction",
+           "fno_truncate", "fno_truncate_rule", "naf_compress", "eigh_sym", "pt2_correction_workspace_size", "pt2_energy_correction",
            "upload_inputs", "profile_enable", "profile_read", "pairscreen_num_params", "pairscreen_features",
            "pairscreen_mlp_forward", "pairscreen_mlp_backward", "pairscreen_adam_step", "pairscreen_train",
            "pairscreen_targets", "pairscreen_build_mask"]
@@ -134,6 +134,48 @@ def fno_truncate(D_vv: torch.Tensor, p_o: float, degen_rel_tol: float = 0.0, *, 
                            ctypes.byref(n_kept), margins, _ptr(ws), ctypes.c_size_t(ws.numel()),
                            _stream(stream)))
     return dict(occ=occ, no_vecs=no_vecs, n_kept=int(n_kept.value), margins=(margins[0], margins[1]))
+
+
+def fno_truncate_rule(D_vv: torch.Tensor, rule: int, param: float, degen_rel_tol: float = 0.0, *, occ=None,
+                      no_vecs=None, workspace=None, stream=None) -> dict:
+    """fno_truncate with an explicit rule (TRUNC_CUMULATIVE p_o, TRUNC_FRACTION p_v,
+    TRUNC_CUTOFF n_kappa, TRUNC_FIXED N')."""
+    lib = _lib.load()
+    n_v = D_vv.shape[0]
+    _need(D_vv, "D_vv", torch.float64, n_v * n_v)
+    dev = D_vv.device
+    if occ is None:
+        occ = torch.empty(n_v, dtype=torch.float64, device=dev)
+    if no_vecs is None:
+        no_vecs = torch.empty((n_v, n_v), dtype=torch.float64, device=dev)
+    _need(occ, "occ", torch.float64, n_v)
+    _need(no_vecs, "no_vecs", torch.float64, n_v * n_v)
+    ws = _workspace(fno_truncate_workspace_size(n_v), dev, workspace)
+    n_kept = ctypes.c_int64(0)
+    margins = (ctypes.c_double * 2)()
+    check(lib.fno_truncate_rule(_ptr(D_vv), n_v, int(rule), float(param), float(degen_rel_tol), _ptr(occ),
+                                _ptr(no_vecs), ctypes.byref(n_kept), margins, _ptr(ws), ctypes.c_size_t(ws.numel()),
+                                _stream(stream)))
+    return dict(occ=occ, no_vecs=no_vecs, n_kept=int(n_kept.value), margins=(margins[0], margins[1]))
+
+
+def naf_compress(opts, B: torch.Tensor, eps: float, *, workspace=None, stream=None) -> dict:
+    """Natural auxiliary functions: returns B_naf [n_h, n_vir, n_naf], sigma [n_aux]
+    (descending) and n_naf."""
+    lib = _lib.load()
+    n_h, n_v, n_aux = opts.n_core + opts.n_act, opts.n_vir, opts.n_aux
+    _need(B, "B", torch.float64, n_h * n_v * n_aux)
+    dev = B.device
+    out = torch.empty(n_h * n_v * n_aux, dtype=torch.float64, device=dev)
+    sigma = torch.empty(n_aux, dtype=torch.float64, device=dev)
+    n = ctypes.c_size_t(0)
+    check(lib.naf_compress_workspace_size(ctypes.byref(opts), ctypes.byref(n)))
+    ws = _workspace(int(n.value), dev, workspace)
+    k = ctypes.c_int64(0)
+    check(lib.naf_compress(ctypes.byref(opts), _ptr(B), float(eps), _ptr(out), _ptr(sigma), ctypes.byref(k),
+                           _ptr(ws), ctypes.c_size_t(ws.numel()), _stream(stream)))
+    k = int(k.value)
+    return dict(B_naf=out[: n_h * n_v * k].view(n_h, n_v, k), sigma=sigma, n_naf=k)
 
 
 def eigh_sym(A: torch.Tensor, *, workspace=None, stream=None):

@@ -26,6 +26,7 @@ SOURCES = [
     "eigh.hip",
     "fno.hip",
     "correction.cpp",
+    "naf.cpp",
     "split.hip",
     "pair_bf16.hip",
     "pair_fp8.hip",

@@ -101,3 +101,29 @@ def test_correction_rejects_bad_kept_count(lib):
     n = ctypes.c_size_t(0)
     assert lib.pt2_correction_workspace_size(ctypes.byref(o), 0, ctypes.byref(n)) == _lib.ERR_INVALID_ARG
     assert lib.pt2_correction_workspace_size(ctypes.byref(o), 61, ctypes.byref(n)) == _lib.ERR_INVALID_ARG
+
+
+@pytest.mark.parametrize("rule,param", [(7, 0.5), (1, 0.0), (1, 1.5), (0, 0.0), (3, 2.5), (3, 0.0), (3, 61.0),
+                                        (2, float("nan"))])
+def test_truncation_rule_arguments_rejected(lib, rule, param):
+    kept = ctypes.c_int64(0)
+    buf = ctypes.create_string_buffer(64)
+    st = lib.fno_truncate_rule(buf, 60, rule, param, 0.0, buf, buf, ctypes.byref(kept), None, buf, 1 << 30, None)
+    assert st == _lib.ERR_INVALID_ARG
+    assert lib.dfpt2_last_error()
+
+
+def test_naf_arguments_rejected(lib):
+    n = ctypes.c_size_t(0)
+    assert lib.naf_compress_workspace_size(ctypes.byref(dp.make_opts(2, 0, 10, 20000, 0.5)),
+                                           ctypes.byref(n)) == _lib.ERR_INVALID_ARG
+    o = dp.make_opts(2, 0, 10, 20, 0.5)
+    assert lib.naf_compress_workspace_size(ctypes.byref(o), ctypes.byref(n)) == _lib.OK and n.value > 0
+    k = ctypes.c_int64(0)
+    buf = ctypes.create_string_buffer(64)
+    assert lib.naf_compress(ctypes.byref(o), buf, float("nan"), buf, buf, ctypes.byref(k), buf, n.value,
+                            None) == _lib.ERR_INVALID_ARG
+    assert lib.naf_compress(ctypes.byref(o), None, 0.0, buf, buf, ctypes.byref(k), buf, n.value,
+                            None) == _lib.ERR_INVALID_ARG
+    assert lib.naf_compress(ctypes.byref(o), buf, 0.0, buf, buf, ctypes.byref(k), buf, 0,
+                            None) == _lib.ERR_WORKSPACE

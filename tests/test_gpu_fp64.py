@@ -162,3 +162,45 @@ def test_fno_near_degeneracy_widening():
     t1 = dp.fno_truncate(torch.from_numpy(D).cuda(), p_o, 0.01)
     assert t0["n_kept"] == o.expand_near_degenerate(occ, o.kept_count_po(occ, p_o)[0], 0.0)
     assert t1["n_kept"] == o.expand_near_degenerate(occ, o.kept_count_po(occ, p_o)[0], 0.01)
+
+
+# -------------------------------------------------- truncation rules (p_v, cutoff, fixed N')
+
+def test_truncation_rules_c1():
+    """Eq. 9 fraction p_v, the occupation cutoff n_kappa and a fixed N' on the c1
+    density, against the oracle's counts on its own occupations; the correction for
+    a p_v-truncated space against the oracle's kept-space energy."""
+    dp = need_gpu()
+    inp = synth.config_inputs("c1")
+    r = o.pt2_pass_inputs(inp, 0.5)
+    occ_ref, vec_ref = o.natural_orbitals(r.D_vv)
+    D = torch.from_numpy(np.ascontiguousarray(r.D_vv)).cuda()
+    n = inp.n_vir
+    for p_v in (1.0 / n, 0.25, 0.5, 40.0 / 60.0, 0.999, 1.0):
+        t = dp.fno_truncate_rule(D, dp.TRUNC_FRACTION, p_v)
+        assert t["n_kept"] == o.kept_count_pv(n, p_v)
+    # cutoffs between occupations (away from ties), below every one, above every one
+    mids = 0.5 * (occ_ref[:-1] + occ_ref[1:])
+    for kappa in list(mids[[0, 5, 20, 39, 58]]) + [0.5 * occ_ref[-1], 2.0 * occ_ref[0]]:
+        t = dp.fno_truncate_rule(D, dp.TRUNC_CUTOFF, float(kappa))
+        assert t["n_kept"] == o.kept_count_cutoff(occ_ref, kappa)
+        if 0 < t["n_kept"] < n:
+            assert t["margins"][0] > 0 and t["margins"][1] > 0
+    for nk in (1, 17, 60):
+        t = dp.fno_truncate_rule(D, dp.TRUNC_FIXED, float(nk))
+        assert t["n_kept"] == nk
+    # cumulative rule through the new entry point = fno_truncate
+    a = dp.fno_truncate(D, 0.985)
+    b = dp.fno_truncate_rule(D, dp.TRUNC_CUMULATIVE, 0.985)
+    assert a["n_kept"] == b["n_kept"] and a["margins"] == b["margins"]
+    # correction on a p_v-truncated space
+    p_v = 0.5
+    t = dp.fno_truncate_rule(D, dp.TRUNC_FRACTION, p_v)
+    nk = o.kept_count_pv(n, p_v)
+    e_kept = o.kept_energy(inp, vec_ref, nk, 0.5)
+    g = gpu_pass(inp, 0.5)
+    d = g["dev"]
+    c = dp.pt2_energy_correction(g["opts"], d["eps_hole"], d["eps_vir"], d["gamma_act"], d["B"], t["no_vecs"],
+                                 t["n_kept"], g["raw"]["e_pt2"])
+    ek = c["e_kept"].cpu().numpy()
+    assert dd_diff((ek[0], ek[1]), e_kept) <= E_TOL
