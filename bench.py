@@ -45,6 +45,9 @@ WORKLOADS = {
     "c3": dict(base="c3", gen=dict()),
     "c2": dict(base="c2", gen=dict(low_rank=64)),
     "c5": dict(base="c5", gen=dict()),
+    # c3 sizes with a redundant auxiliary set (rank 2000 of 4000 up to 1e-7 noise): the
+    # input natural auxiliary functions compress (--naf-scan)
+    "c4naf": dict(base="c4", gen=dict(aux_rank=2000, aux_noise=1e-7)),
 }
 
 
@@ -137,6 +140,9 @@ def main():
     ap.add_argument("--no-fp64-ref", action="store_true")
     ap.add_argument("--s", type=float, default=None)
     ap.add_argument("--p-o", type=float, default=None)
+    ap.add_argument("--naf-scan", action="store_true",
+                    help="after the timed steps: natural auxiliary functions at several relative thresholds, "
+                         "the compression time, n_naf, and the pass time and energy on the compressed integrals")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="run one device-to-device copy of this many MiB before timing (a reference "
                          "kernel of known traffic for hardware-counter runs)")
@@ -303,6 +309,29 @@ def main():
            "roofline": roofline}
     if train_info:
         out["screen_training"] = train_info
+    if args.naf_scan:
+        scan = []
+        E_full = (float(E[0]), float(E[1]))
+        for rel in (1e-10, 1e-8, 1e-6, 1e-4):
+            e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+            e0.record(stream)
+            nr = dp.naf_compress(opts, d["B"], rel, stream=stream)
+            e1.record(stream)
+            k = nr["n_naf"]
+            ok = dp.make_opts(n_core, n_act, n_v, k, s, precision=prec)
+            rk = dp.build_vv_density(ok, d["eps_hole"], d["eps_vir"], d["gamma_act"], nr["B_naf"].contiguous(),
+                                     stream=stream)
+            e2.record(stream)
+            torch.cuda.synchronize()
+            Ek = rk["e_pt2"].cpu().numpy()
+            scan.append({"rel_threshold": rel, "n_naf": k, "naf_ms": e0.elapsed_time(e1),
+                         "pass_ms": e1.elapsed_time(e2),
+                         "delta_E_vs_uncompressed_Eh": dd((float(Ek[0]), float(Ek[1])), E_full)})
+            log(f"NAF rel {rel:g}: n_naf {k} of {n_aux}, {scan[-1]['naf_ms']:.0f} ms + pass {scan[-1]['pass_ms']:.0f} ms,"
+                f" dE {scan[-1]['delta_E_vs_uncompressed_Eh']:.3e}")
+            del nr, rk
+            torch.cuda.empty_cache()
+        out["naf_scan"] = scan
     if ref is not None:
         out["fp64_ms_per_pass"] = ref["ms"]
         out["speedup_vs_fp64"] = ref["ms"] / ms_pass

@@ -171,8 +171,9 @@ int naf_compress_workspace_size(const dfpt2_opts* opts, size_t* bytes);
 /*
  * Natural auxiliary functions (the auxiliary-basis compression the paper's
  * conclusions propose for this pass; Kallay's NAFs): with J[(i,a), P] = B^P_ia,
- * W = J^T J = U diag(sigma) U^T, keep the n_naf functions with sigma_k > eps
- * (eps <= 0 keeps all: then V = B B^T is reproduced to rounding) and form
+ * W = J^T J = U diag(sigma) U^T (sigma descending), keep the n_naf functions
+ * with sigma_k > eps sigma_0 (a threshold relative to the largest eigenvalue;
+ * eps <= 0 keeps all: then V = B B^T is reproduced to rounding) and form
  * B~^k_ia = sum_P B^P_ia U_Pk.
  *   opts    sizes only (n_core + n_act holes, n_vir, n_aux <= 16384)
  *   B       [n_h][n_vir][n_aux] as for dfpt2_build_vv_density

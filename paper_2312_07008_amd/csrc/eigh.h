@@ -12,8 +12,10 @@ constexpr int kEighMaxN = 16384;
 
 size_t eigh_workspace_bytes(int n);
 // w_out [n] and Z_out [n][n] (column k = eigenvector of w_out[k]); ascending, or
-// descending when `descending` is set.  Synchronizes the stream.
+// descending when `descending` is set.  With vec_floor_rel > 0 only eigenvalues
+// above vec_floor_rel * max|w| get eigenvectors (the other columns are zero).
+// Synchronizes the stream.
 int eigh_run(const double* A, int n, double* w_out, double* Z_out, char* ws, size_t ws_bytes, hipStream_t st,
-             int descending);
+             int descending, double vec_floor_rel = -1.0);
 
 }  // namespace dfpt2

@@ -272,20 +272,31 @@ __device__ void lu_solve(int s, int t, const LuCols& L, int n, int g, double* X,
 
 // Group leaders (first eigenvalue of a near-degenerate run inside a block) compute
 // the vectors of their whole group; X is row-major n x n, column g = vector g.
+// vec_floor: if non-null, eigenvectors are formed only for eigenvalues above
+// *vec_floor; the other columns of X are zero (callers that drop those
+// eigenpairs, such as the NAF compression, skip the cost of large clusters).
 __global__ void tridiag_inverse_iteration(int n, const double* d, const double* e, const int* blk_start,
                                           const int* blk_end, const double* tnorm, const double* lam,
-                                          LuCols L, double* X, int* status) {
+                                          LuCols L, double* X, int* status, const double* vec_floor) {
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= n) return;
   const int s = blk_start[g], t = blk_end[g];
+  if (vec_floor && !(lam[g] > *vec_floor)) {
+    for (int i = 0; i < n; ++i) X[(size_t)i * n + g] = 0.0;
+    return;
+  }
   const double nrm = (*tnorm > 0.0) ? *tnorm : 1.0;
   const double grp_tol = 1e-10 * nrm;
   if (t - s == 1) {  // a 1 x 1 block: the unit vector
     for (int i = 0; i < n; ++i) X[(size_t)i * n + g] = (i == s) ? 1.0 : 0.0;
     return;
   }
-  // leader test: previous eigenvalue in the same block is not within grp_tol
-  if (g > s && fabs(lam[g] - lam[g - 1]) <= grp_tol) return;
+  // a leader above the floor starts its group; earlier members below the floor were zeroed
+  if (vec_floor && g > s && fabs(lam[g] - lam[g - 1]) <= grp_tol && !(lam[g - 1] > *vec_floor)) {
+    // lam[g - 1] was skipped: g leads what remains of the group
+  } else if (g > s && fabs(lam[g] - lam[g - 1]) <= grp_tol) {
+    return;
+  }
   int g1 = g + 1;
   while (g1 < t && fabs(lam[g1] - lam[g1 - 1]) <= grp_tol) ++g1;
   const double tiny = DBL_EPSILON * nrm;
@@ -435,6 +446,19 @@ __global__ void eig_permute(int n, const double* lam, const int* rank, const dou
   for (int i = threadIdx.x; i < n; i += blockDim.x) Z_out[(size_t)i * n + dst] = sgn * Zin[(size_t)i * n + g];
 }
 
+// *floor = rel * (largest eigenvalue magnitude)
+__global__ void lam_floor(int n, const double* lam, double rel, double* floor) {
+  __shared__ double m[64];
+  double v = 0.0;
+  for (int i = threadIdx.x; i < n; i += 64) v = fmax(v, fabs(lam[i]));
+  m[threadIdx.x] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int i = 1; i < 64; ++i) v = fmax(v, m[i]);
+    *floor = rel * fmax(v, m[0]);
+  }
+}
+
 __global__ void zero_int(int* p, int n) {
   for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0;
 }
@@ -456,7 +480,7 @@ size_t eigh_workspace_bytes(int n) {
 }
 
 int eigh_run(const double* A_in, int n, double* w_out, double* Z_out, char* ws, size_t ws_bytes, hipStream_t st,
-             int descending) {
+             int descending, double vec_floor_rel) {
   if (n < 1 || n > kEighMaxN) return fail(DFPT2_ERR_INVALID_ARG, "eigh: n=%d outside [1, %d]", n, kEighMaxN);
   if (ws_bytes < eigh_workspace_bytes(n)) return fail(DFPT2_ERR_WORKSPACE, "eigh workspace too small");
   const size_t nn = (size_t)n * n;
@@ -503,8 +527,13 @@ int eigh_run(const double* A_in, int n, double* w_out, double* Z_out, char* ws, 
                      lam);
   // 3. inverse iteration
   LuCols L{lu, lu + nn, lu + 2 * nn, lu + 3 * nn, lu + 4 * nn};
+  const double* floor_ptr = nullptr;
+  if (vec_floor_rel > 0.0) {
+    hipLaunchKernelGGL(lam_floor, dim3(1), dim3(64), 0, st, n, lam, vec_floor_rel, tnorm + 1);
+    floor_ptr = tnorm + 1;
+  }
   hipLaunchKernelGGL(tridiag_inverse_iteration, dim3((n + 63) / 64), dim3(64), 0, st, n, d, e, blk_start, blk_end,
-                     tnorm, lam, L, X, status);
+                     tnorm, lam, L, X, status, floor_ptr);
   // 4. back-transformation
   if (n > 2) {
     int cw = 8;

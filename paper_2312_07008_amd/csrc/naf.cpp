@@ -3,11 +3,15 @@
 // With J[(i,a), P] = B^P_ia over every hole i and virtual a:
 //   W = J^T J (FP64 MFMA GEMM, contraction over n_h n_vir), W = U diag(sigma) U^T
 //   with the library's eigensolver (sigma descending), keep the n_naf functions
-//   with sigma_k > eps (eps <= 0 keeps all), B~ = J U[:, :n_naf].
+//   with sigma_k > eps max|sigma| = eps sigma_0 (eps <= 0 keeps all), B~ = J U[:, :n_naf].
+// Eigenvectors are formed only for the kept functions: dropped ones often form a
+// large cluster near zero (redundant auxiliary sets), which inverse iteration
+// would otherwise orthogonalize serially.
 // B~ is laid out like B with n_aux replaced by n_naf, so it can be passed to
 // dfpt2_build_vv_density and pt2_energy_correction as is.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <vector>
 
@@ -82,7 +86,7 @@ int naf_compress(const dfpt2_opts* opts, const double* B, double eps, double* B_
     if ((e = gemm_f64(B, na, 0, 1, B, na, 0, 0, W, na, 0, na, na, (int)p.rows, 1, 1.0, 0.0, s)) != hipSuccess)
       return hip_fail(e, "NAF metric GEMM");
   }
-  st = eigh_run(W, na, sigma, U, ws + p.off_eig, p.eig_bytes, s, 1);
+  st = eigh_run(W, na, sigma, U, ws + p.off_eig, p.eig_bytes, s, 1, eps > 0.0 ? eps : -1.0);
   if (st != DFPT2_OK) return st;
   std::vector<double> h(na);
   if ((e = hipMemcpyAsync(h.data(), sigma, sizeof(double) * na, hipMemcpyDeviceToHost, s)) != hipSuccess)
@@ -91,7 +95,9 @@ int naf_compress(const dfpt2_opts* opts, const double* B, double eps, double* B_
   int keep = na;
   if (eps > 0.0) {
     keep = 0;
-    while (keep < na && h[keep] > eps) ++keep;
+    // the eigensolver forms vectors above eps max|sigma| (= eps sigma_0 for the PSD metric)
+    const double thr = eps * std::max(std::fabs(h[0]), std::fabs(h[na - 1]));
+    while (keep < na && h[keep] > thr) ++keep;
   }
   for (int k = 0; k < na; ++k)
     if (!std::isfinite(h[k])) return fail(DFPT2_ERR_NONFINITE, "non-finite NAF eigenvalue");

@@ -29,8 +29,13 @@ this order:
   5. (low-rank variant only) P ~ N(0,1)^(n_aux x 64), R ~ N(0,1)^(64 x n_h*n_v)
   6. (localized variant only) hole positions x_i ~ U[0, 40], aux positions
      y_Q ~ U[0, 40]
+  7. (redundant-auxiliary variant only, rank r) C ~ N(0,1)^(n_aux x r),
+     Y ~ N(0,1)^(r x n_h*n_v); Z is then scaled by the noise level nu
   B^Q_ia = d_a * (Z^Q_ia [+ (P R)^Q_ia / 8]) [* exp(-|x_i - y_Q| / xi)],
-  with the virtual decay d_a = 0.3 / (1 + eps_a) * 0.2.
+  with the virtual decay d_a = 0.3 / (1 + eps_a) * 0.2; in the redundant-auxiliary
+  variant B^Q_ia = d_a * ((C Y)^Q_ia / sqrt(r) + nu Z^Q_ia): n_aux functions that
+  span only an r-dimensional space up to noise, the situation of a large
+  automatically generated auxiliary set that natural auxiliary functions compress.
 
 Holes are ordered core first, then active.  B is returned in the layout the
 library consumes, ``B[i, a, Q]`` (hole, virtual, auxiliary; auxiliary fastest),
@@ -93,6 +98,7 @@ def _haar_orthogonal(rng: np.random.Generator, n: int) -> np.ndarray:
 
 def generate(n_core: int, n_act: int, n_vir: int, n_aux: int, seed: int = 0, *,
              low_rank: int = 0, localized_xi: Optional[float] = None,
+             aux_rank: int = 0, aux_noise: float = 0.0,
              q_chunk: int = 256, label: str = "") -> Inputs:
     """Draw one input set following the recipe in the module docstring."""
     if n_act % 2:
@@ -124,6 +130,15 @@ def generate(n_core: int, n_act: int, n_vir: int, n_aux: int, seed: int = 0, *,
         for q0 in range(0, n_aux, q_chunk):
             q1 = min(n_aux, q0 + q_chunk)
             add = (p[q0:q1] @ r).reshape(q1 - q0, n_h, n_vir) * scale
+            B[:, :, q0:q1] += add.transpose(1, 2, 0)
+    if aux_rank:
+        B *= aux_noise
+        c = rng.standard_normal((n_aux, aux_rank))
+        y = rng.standard_normal((aux_rank, n_h * n_vir))
+        scale = 1.0 / np.sqrt(aux_rank)
+        for q0 in range(0, n_aux, q_chunk):
+            q1 = min(n_aux, q0 + q_chunk)
+            add = (c[q0:q1] @ y).reshape(q1 - q0, n_h, n_vir) * scale
             B[:, :, q0:q1] += add.transpose(1, 2, 0)
     B *= d[None, :, None]
     if localized_xi is not None:

@@ -38,7 +38,7 @@ def test_naf_eigenvalues_count_and_pass(sizes, loc):
     assert np.abs(g["D"] - full.D_vv).max() <= 1e-11 * np.abs(full.D_vv).max()
     # truncating thresholds between eigenvalues: the same count and the same compressed pass
     for k in (inp.n_aux // 2, inp.n_aux // 5):
-        eps = 0.5 * (sig_ref[k - 1] + sig_ref[k])
+        eps = 0.5 * (sig_ref[k - 1] + sig_ref[k]) / sig_ref[0]
         r = _run(inp, eps)
         Bt, _, nk = naf.naf_compress(inp.B, eps)
         assert r["n_naf"] == nk == k
@@ -56,4 +56,19 @@ def test_naf_threshold_above_all_rejected():
     d = dp.upload_inputs(inp)
     opts = dp.make_opts(inp.n_core, inp.n_act, inp.n_vir, inp.n_aux, 0.5)
     with pytest.raises(dp.DfptError):
-        dp.naf_compress(opts, d["B"], 1e300)
+        dp.naf_compress(opts, d["B"], 2.0)
+
+
+def test_naf_redundant_auxiliary_set():
+    """A rank-r auxiliary set up to 1e-7 noise: the relative threshold 1e-8 keeps r
+    functions, eigenvectors are formed only for them (the near-zero cluster is
+    skipped), and the pass on the compressed integrals matches the oracle's."""
+    inp = synth.generate(6, 0, 80, 300, seed=2, aux_rank=40, aux_noise=1e-7)
+    r = _run(inp, 1e-8)
+    Bt, sig, nk = naf.naf_compress(inp.B, 1e-8)
+    assert r["n_naf"] == nk == 40
+    full = o.pt2_pass_inputs(inp, 0.5)
+    g = gpu_pass(inp.replace(B=r["B_naf"].cpu().numpy()), 0.5)
+    print(f"  redundant set: dE vs uncompressed {dd_diff(g['energy'], full.energy):.2e}", flush=True)
+    assert dd_diff(g["energy"], o.pt2_pass_inputs(inp.replace(B=Bt), 0.5).energy) <= E_TOL
+    assert dd_diff(g["energy"], full.energy) <= 1e-6 * abs(full.E)

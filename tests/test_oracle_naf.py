@@ -23,7 +23,7 @@ def test_dropped_norm_equals_dropped_eigenvalues():
     """sum ||B||^2 - sum ||B~||^2 = sum of the dropped sigma (trace of W)."""
     inp = synth.generate(4, 0, 30, 50, seed=1, localized_xi=2.0)
     sigma_all = naf.naf_compress(inp.B, 0.0)[1]
-    eps = float(sigma_all[20])                  # keeps exactly 20 functions (no ties)
+    eps = float(sigma_all[20] / sigma_all[0])   # keeps exactly 20 functions (no ties)
     Bt, sigma, n = naf.naf_compress(inp.B, eps)
     assert n == 20
     dropped = np.sum(inp.B ** 2) - np.sum(Bt ** 2)
@@ -41,7 +41,7 @@ def test_rank_r_integrals_compress_exactly():
     C = rng.standard_normal((r, n_aux))
     B = 0.05 * np.einsum("iar,rP->iaP", Z, C)
     inp = synth.generate(n_h, 0, n_v, n_aux, seed=3).replace(B=B)
-    Bt, sigma, n = naf.naf_compress(B, 1e-10 * np.sum(B ** 2))
+    Bt, sigma, n = naf.naf_compress(B, 1e-10)
     assert n == r
     a = o.pt2_pass_inputs(inp, 0.7)
     b = o.pt2_pass_inputs(inp.replace(B=Bt), 0.7)
@@ -57,7 +57,7 @@ def test_orthogonal_columns_closed_form():
     norms = np.array([3.0, 2.0, 1.5, 0.5, 0.1])
     J = Q * norms
     B = J.reshape(3, 20, 5)
-    Bt, sigma, n = naf.naf_compress(B, 0.2)
+    Bt, sigma, n = naf.naf_compress(B, 0.2 / 9.0)
     np.testing.assert_allclose(sigma, norms ** 2, rtol=1e-12)
     assert n == 4
     Jt = Bt.reshape(60, 4)
