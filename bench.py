@@ -18,7 +18,7 @@ Untimed setup: the screening network is trained on plain-pass labels of 200
 small (10 holes, 60 virtuals, 200 aux) input sets, and the plain FP64 pass on the
 workload is timed once as the reference the mixed pass is judged against.
 
-    python bench.py [--steps K] [--warmup W] [--workload c4] [--precision bf16|fp8|fp64] [--no-screen]
+    python bench.py [--steps K] [--warmup W] [--workload c4] [--precision int8|bf16|fp8|fp64] [--no-screen]
 """
 from __future__ import annotations
 
@@ -34,7 +34,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "D_vv build GFLOP/s & ms/pass, mixed+screened vs FP64 at |ΔE|≤1e-6 Eh"
-PEAK_TFLOPS = {"f64": 78.6, "bf16": 2500.0, "fp8": 5000.0}
+PEAK_TFLOPS = {"f64": 78.6, "bf16": 2500.0, "fp8": 5000.0, "i8": 5000.0}  # dense MFMA (int8: TOP/s)
 SCREEN_THRESHOLD = 1e-6
 
 WORKLOADS = {
@@ -134,7 +134,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="c4", choices=sorted(WORKLOADS))
-    ap.add_argument("--precision", default="bf16", choices=["bf16", "fp8", "fp64"])
+    ap.add_argument("--precision", default="bf16", choices=["int8", "bf16", "fp8", "fp64"])
     ap.add_argument("--no-screen", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-ref", action="store_true")
@@ -162,8 +162,8 @@ def main():
     cfg = synth.CONFIGS[wl["base"]]
     s = args.s if args.s is not None else cfg["s"][0]
     p_o = args.p_o if args.p_o is not None else cfg["p_o"][0]
-    prec = {"fp64": dp.FP64, "bf16": dp.BF16_SLICED, "fp8": dp.FP8_SLICED}[args.precision]
-    dtype = {"fp64": "f64", "bf16": "bf16", "fp8": "fp8"}[args.precision]
+    prec = {"fp64": dp.FP64, "bf16": dp.BF16_SLICED, "fp8": dp.FP8_SLICED, "int8": dp.INT8_SLICED}[args.precision]
+    dtype = {"fp64": "f64", "bf16": "bf16", "fp8": "fp8", "int8": "i8"}[args.precision]
     screen = not args.no_screen
 
     t0 = time.time()
@@ -268,7 +268,7 @@ def main():
 
     # dominant kernel: the pair kernel (V = B_i B_j^T + fused epilogue); issued MFMA flops:
     # 2 n_v^2 n_aux per computed unordered core pair and per operand-slice product
-    ns1 = 1 if args.precision == "fp64" else 4
+    ns1 = {"fp64": 1, "int8": 5}.get(args.precision, 4)
     products = ns1 * (ns1 + 1) // 2
     tr, c, nd = records[-1][1], records[-1][2], records[-1][3]
     n_up = n_core * (n_core + 1) // 2
@@ -277,11 +277,12 @@ def main():
     screen_drops = nd > 0  # a different set of launches than the counters were taken on
     achieved = (products * 2.0 * n_v * n_v * n_aux * computed * args.steps) / (pk_ms * 1e-3) / 1e12 if pk_launch else None
     peak = PEAK_TFLOPS[dtype]
-    roofline = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+    kname = {"int8": "i8"}.get(args.precision, args.precision)
+    roofline = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TOP/s" if dtype == "i8" else "TFLOP/s",
                 "frac": (achieved / peak) if achieved else None,
-                "traffic": recorded_traffic(f"pair_gemm_{args.precision}_kernel<{ns1},true>", args.workload)
+                "traffic": recorded_traffic(f"pair_gemm_{kname}_kernel<{ns1},true>", args.workload)
                 if (ns1 > 1 and not screen_drops) else None,
-                "kernel": f"pair_gemm_{args.precision if ns1 > 1 else 'f64'} (V = B_i B_j^T, {products} slice products, "
+                "kernel": f"pair_gemm_{kname if ns1 > 1 else 'f64'} (V = B_i B_j^T, {products} slice products, "
                           "fused DSRG epilogue)",
                 "traffic_unit": "HBM-side bytes per launch: FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 (factors from a "
                                 "1 GiB device copy), from the committed counter summary under profiles/",

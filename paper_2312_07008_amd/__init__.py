@@ -4,7 +4,7 @@ The computation lives in libdfpt2.so (hand-written HIP for gfx950, C ABI in
 include/dfpt2.h).  This package only loads it and marshals torch device
 tensors into its entry points; there is no CPU fallback.
 """
-from ._lib import (BF16_SLICED, FP8_SLICED, FP64, DfptError, Opts, LIB_PATH, load,  # noqa: F401
+from ._lib import (BF16_SLICED, FP8_SLICED, FP64, INT8_SLICED, DfptError, Opts, LIB_PATH, load,  # noqa: F401
                    TRUNC_CUMULATIVE, TRUNC_CUTOFF, TRUNC_FIXED, TRUNC_FRACTION)
 from .api import (pairscreen_adam_step, pairscreen_build_mask, pairscreen_features,  # noqa: F401
                   pairscreen_mlp_backward, pairscreen_mlp_forward, pairscreen_num_params, pairscreen_targets,

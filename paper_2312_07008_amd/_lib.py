@@ -18,6 +18,7 @@ ERR_UNSUPPORTED = -6
 FP64 = 0
 BF16_SLICED = 1
 FP8_SLICED = 2
+INT8_SLICED = 3
 TRUNC_CUMULATIVE, TRUNC_FRACTION, TRUNC_CUTOFF, TRUNC_FIXED = 0, 1, 2, 3
 
 

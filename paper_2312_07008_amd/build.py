@@ -30,6 +30,7 @@ SOURCES = [
     "split.hip",
     "pair_bf16.hip",
     "pair_fp8.hip",
+    "pair_i8.hip",
     "split_t.hip",
     "density_bf16.hip",
     "active.hip",

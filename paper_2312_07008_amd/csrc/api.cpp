@@ -46,7 +46,8 @@ int plan_pass(const dfpt2_opts* o, PassPlan* pl, bool energy_only) {
   if (!(o->s > 0.0) || !std::isfinite(o->s)) return fail(DFPT2_ERR_INVALID_ARG, "s must be finite and > 0");
   if (o->density_convention != 0 && o->density_convention != 1)
     return fail(DFPT2_ERR_INVALID_ARG, "density_convention must be 0 or 1");
-  if (o->precision != DFPT2_FP64 && o->precision != DFPT2_BF16_SLICED && o->precision != DFPT2_FP8_SLICED)
+  if (o->precision != DFPT2_FP64 && o->precision != DFPT2_BF16_SLICED && o->precision != DFPT2_FP8_SLICED &&
+      o->precision != DFPT2_INT8_SLICED)
     return fail(DFPT2_ERR_INVALID_ARG, "unknown precision %d", o->precision);
   if (o->slices_gemm1 < 0 || o->slices_gemm1 > 8 || o->slices_gemm2 < 0 || o->slices_gemm2 > 8)
     return fail(DFPT2_ERR_INVALID_ARG, "slice counts must lie in [0, 8]");
@@ -88,11 +89,19 @@ int plan_pass(const dfpt2_opts* o, PassPlan* pl, bool energy_only) {
   p.n_v_pad = p.n_v_pad_d;  // slab rows of the sliced operands
   p.nTP1 = p.nTP;
   p.n_aux_pad = p.precision == DFPT2_FP8_SLICED ? (p.n_aux + 63) / 64 * 64 : (p.n_aux + 31) / 32 * 32;
-  if (p.precision != DFPT2_FP64 && (p.ns1 < 2 || p.ns1 > 4))
+  if ((p.precision == DFPT2_BF16_SLICED || p.precision == DFPT2_FP8_SLICED) && (p.ns1 < 2 || p.ns1 > 4))
     return fail(DFPT2_ERR_INVALID_ARG, "slices_gemm1 must lie in [2, 4] for BF16 and FP8 slicing");
-  p.ns2 = o->slices_gemm2 ? o->slices_gemm2 : (p.precision == DFPT2_BF16_SLICED ? 4 : 1);
-  if (p.ns2 > 4 || (p.ns2 > 1 && p.precision != DFPT2_BF16_SLICED))
-    return fail(DFPT2_ERR_INVALID_ARG, "slices_gemm2 must be 1 (FP64 density) or, with BF16 precision, 2..4");
+  if (p.precision == DFPT2_INT8_SLICED) {
+    if (p.ns1 < 3 || p.ns1 > 5) return fail(DFPT2_ERR_INVALID_ARG, "slices_gemm1 must lie in [3, 5] for INT8 digits");
+    if (p.n_aux_pad > pair_i8_max_aux_pad(p.ns1))
+      return fail(DFPT2_ERR_INVALID_ARG, "n_aux=%d too large for exact INT8 level sums with %d digits (max %d)",
+                  p.n_aux, p.ns1, pair_i8_max_aux_pad(p.ns1));
+  }
+  const bool sliced_density = p.precision == DFPT2_BF16_SLICED || p.precision == DFPT2_INT8_SLICED;
+  p.ns2 = o->slices_gemm2 ? o->slices_gemm2 : (sliced_density ? 4 : 1);
+  if (p.ns2 > 4 || (p.ns2 > 1 && !sliced_density))
+    return fail(DFPT2_ERR_INVALID_ARG,
+                "slices_gemm2 must be 1 (FP64 density) or, with BF16 or INT8 precision, 2..4");
   if (energy_only) p.ns2 = 1;
   // split-BF16 density: splits of the pair range chosen so that tile pairs x splits
   // fill whole rounds of two workgroups per CU on 256 CUs
@@ -126,11 +135,14 @@ int plan_pass(const dfpt2_opts* o, PassPlan* pl, bool energy_only) {
   p.off_pe = take(sizeof(double) * 2 * (size_t)(p.n_up > 0 ? p.n_up : 1));
   p.off_tn2 = take(sizeof(double) * (size_t)(p.n_up > 0 ? p.n_up : 1));
   p.off_Dpart = take(energy_only ? 0 : sizeof(double) * mat * p.nsplit_all);
-  const size_t slice_bytes = p.precision == DFPT2_BF16_SLICED ? sizeof(__bf16) : p.precision == DFPT2_FP8_SLICED ? 1 : 0;
+  const size_t slice_bytes = p.precision == DFPT2_BF16_SLICED                                        ? sizeof(__bf16)
+                             : (p.precision == DFPT2_FP8_SLICED || p.precision == DFPT2_INT8_SLICED) ? 1
+                                                                                                    : 0;
   p.off_Bs = take(slice_bytes * p.ns1 * p.n_h * p.n_v_pad * p.n_aux_pad);
   p.off_scales = take(p.precision == DFPT2_FP8_SLICED ? sizeof(uint32_t) * 2 * (size_t)p.n_h * p.n_v_pad * (p.n_aux_pad / 64)
                                                       : 0);
   p.off_norm2 = take(p.precision != DFPT2_FP64 ? sizeof(double) * (size_t)p.n_h * p.n_v : 0);
+  p.off_rexp = take(p.precision == DFPT2_INT8_SLICED ? sizeof(int) * (size_t)p.n_h * p.n_v_pad : 0);
   p.off_Ts = take(p.ns2 >= 2 ? sizeof(__bf16) * 4 * (size_t)p.batch * p.n_v_pad_d * p.n_v_pad_d * p.ns2 : 0);
   p.off_dg = take(p.ns2 >= 2 ? sizeof(double) * (size_t)p.batch * (p.n_v_pad_d / 64) * p.n_v_pad_d : 0);
   p.off_tmax = take(p.ns2 >= 2 ? sizeof(unsigned long long) * 4 * (size_t)p.batch * p.n_v_pad_d : 0);
@@ -227,13 +239,16 @@ int dfpt2_build_vv_density(const dfpt2_opts* opts, const double* eps_hole, const
 
 namespace dfpt2 {
 
-int default_slices_gemm1(int precision) { return precision == DFPT2_FP64 ? 1 : 4; }
+int default_slices_gemm1(int precision) {
+  return precision == DFPT2_FP64 ? 1 : precision == DFPT2_INT8_SLICED ? 5 : 4;
+}
 
 hipError_t launch_pair(const PairLaunch& L, const PairKernelArgs& a, int n_pairs, hipStream_t st) {
   if (L.precision == DFPT2_FP64) return launch_pair_gemm_f64(a, n_pairs, st);
   PairSlicedArgs b{};
   b.Bs = L.Bs;
   b.scales = L.scales;
+  b.rexp = L.rexp;
   b.norm2 = L.norm2;
   b.eps_h = a.eps_h;
   b.eps_v = a.eps_v;
@@ -242,7 +257,7 @@ hipError_t launch_pair(const PairLaunch& L, const PairKernelArgs& a, int n_pairs
   b.Vr = a.Vr;
   b.epart = a.epart;
   b.tpart = a.tpart;
-  b.tmax = L.precision == DFPT2_BF16_SLICED ? a.tmax : nullptr;
+  b.tmax = (L.precision == DFPT2_BF16_SLICED || L.precision == DFPT2_INT8_SLICED) ? a.tmax : nullptr;
   b.dgp = b.tmax ? a.dgp : nullptr;
   b.n_v = a.n_v;
   b.n_v_pad = L.n_v_pad;
@@ -252,8 +267,9 @@ hipError_t launch_pair(const PairLaunch& L, const PairKernelArgs& a, int n_pairs
   b.n_v_pad_d = (a.n_v + 63) / 64 * 64;
   b.s = a.s;
   b.e_weight = a.e_weight;
-  return L.precision == DFPT2_FP8_SLICED ? launch_pair_gemm_fp8(b, L.ns, n_pairs, st)
-                                         : launch_pair_gemm_bf16(b, L.ns, n_pairs, st);
+  if (L.precision == DFPT2_FP8_SLICED) return launch_pair_gemm_fp8(b, L.ns, n_pairs, st);
+  if (L.precision == DFPT2_INT8_SLICED) return launch_pair_gemm_i8(b, L.ns, n_pairs, st);
+  return launch_pair_gemm_bf16(b, L.ns, n_pairs, st);
 }
 
 // Active blocks of the pass (row a6): core-active pairs in batches of cores, then
@@ -398,7 +414,7 @@ int run_pass(const PassPlan& pl, const dfpt2_opts& o, const double* eps_h, const
   double* Dpart = reinterpret_cast<double*>(ws + pl.off_Dpart);
   const size_t mat = (size_t)pl.n_v * pl.n_v;
 
-  PairLaunch L{pl.precision, pl.ns1, B, nullptr, nullptr, pl.n_v_pad, pl.n_aux_pad, nullptr};
+  PairLaunch L{pl.precision, pl.ns1, B, nullptr, nullptr, nullptr, pl.n_v_pad, pl.n_aux_pad, nullptr};
   if (pl.precision != DFPT2_FP64) {
     ProfScope ps(DFPT2_STAGE_SPLIT, s);
     double* nrm = reinterpret_cast<double*>(ws + pl.off_norm2);
@@ -407,6 +423,12 @@ int run_pass(const PassPlan& pl, const dfpt2_opts& o, const double* eps_h, const
     if (pl.precision == DFPT2_BF16_SLICED) {
       if ((e = launch_split_rows_bf16(B, pl.n_aux, pl.n_h, pl.n_v, pl.n_v_pad, pl.n_aux, pl.n_aux_pad, pl.ns1,
                                       reinterpret_cast<__bf16*>(ws + pl.off_Bs), nrm, s)) != hipSuccess)
+        return hip_fail(e, "split");
+    } else if (pl.precision == DFPT2_INT8_SLICED) {
+      int* rexp = reinterpret_cast<int*>(ws + pl.off_rexp);
+      L.rexp = rexp;
+      if ((e = launch_split_rows_i8(B, pl.n_aux, pl.n_h, pl.n_v, pl.n_v_pad, pl.n_aux, pl.n_aux_pad, pl.ns1,
+                                    reinterpret_cast<int8_t*>(ws + pl.off_Bs), rexp, nrm, s)) != hipSuccess)
         return hip_fail(e, "split");
     } else {
       uint32_t* sc = reinterpret_cast<uint32_t*>(ws + pl.off_scales);

@@ -32,7 +32,7 @@ struct PassPlan {
   int ns1;          // slices per operand of the pair product (mixed precision)
   int n_v_pad, n_aux_pad;  // slab rows and columns of the sliced operands
   int n_v_pad_d;           // 64-multiple of n_v: layout of the density slices and row data
-  size_t off_pairs, off_count, off_T, off_epart, off_tpart, off_pe, off_tn2, off_Dpart, off_Bs, off_scales, off_norm2, off_Ts, off_dg, off_tmax, off_diag;
+  size_t off_pairs, off_count, off_T, off_epart, off_tpart, off_pe, off_tn2, off_Dpart, off_Bs, off_scales, off_norm2, off_rexp, off_Ts, off_dg, off_tmax, off_diag;
   // active holes
   int n_ca, n_aa_un, cpb, act_cap;
   size_t off_act_T, off_act_V, off_act_Tr, off_act_Vr, off_act_pairs, off_act_slots, off_act_pairs2,
@@ -49,13 +49,15 @@ int run_pass(const PassPlan& pl, const dfpt2_opts& o, const double* eps_h, const
              double* pair_energy, float* pair_tnorm, char* ws, hipStream_t s);
 
 // Pair-kernel launcher shared by the pass and the kept-space energy: FP64, or
-// split BF16 / FP8 from the slices in `Bs` (and FP8 block scales in `scales`),
+// split BF16 / FP8 / INT8 from the slices in `Bs` (and FP8 block scales in
+// `scales`, INT8 row exponents in `rexp`),
 // prepared by the caller.
 struct PairLaunch {
   int precision, ns;
   const double* B;
   const void* Bs;
   const uint32_t* scales;
+  const int* rexp;  // INT8 row exponents
   int n_v_pad, n_aux_pad;
   const double* norm2;
 };

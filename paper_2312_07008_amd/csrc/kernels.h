@@ -26,7 +26,9 @@ hipError_t launch_pair_gemm_f64(const PairKernelArgs& a, int n_pairs, hipStream_
 struct PairSlicedArgs {
   const void* Bs;       // BF16: [n_h][n_v_pad][n_aux_pad/16][ns][16] slices (split.hip)
                         // FP8:  [n_h][n_v_pad][n_aux_pad/64][ns][64] e4m3 slices (split.hip)
+                        // INT8: [n_h][n_aux_pad/32][n_v_pad][ns][32] balanced base-256 digits (split.hip)
   const uint32_t* scales;  // FP8 only: [n_h][n_v_pad][n_aux_pad/64][2] E8M0 scale words
+  const int* rexp;      // INT8 only: [n_h][n_v_pad] row exponents (row value = 2^rexp sum_t d_t 2^-8t)
   const double* norm2;  // [n_h][n_v] ||B_ia||^2 in FP64: exact diagonal of V^{ii}
   const double* eps_h;
   const double* eps_v;
@@ -35,7 +37,7 @@ struct PairSlicedArgs {
   double* Vr;           // [n_pairs][n_v][n_v] renormalized integrals out, or null
   double* epart;
   double* tpart;
-  unsigned long long* tmax;  // BF16 only, or null: [n_pairs][4][n_v_pad] row maxima for the density slices
+  unsigned long long* tmax;  // BF16 / INT8 only, or null: [n_pairs][4][n_v_pad] row maxima for the density slices
   double* dgp;               // with tmax: [n_pairs][nt][n_v_pad] diagonal partial sums (split_t.hip)
   int n_v, n_v_pad, n_aux_pad, nt, nTP;  // n_v_pad: slab rows of Bs; nt: 64-wide tiles of n_v;
                                         // nTP: workgroup tiles per pair
@@ -46,12 +48,17 @@ struct PairSlicedArgs {
 };
 hipError_t launch_pair_gemm_bf16(const PairSlicedArgs& a, int ns, int n_pairs, hipStream_t st);
 hipError_t launch_pair_gemm_fp8(const PairSlicedArgs& a, int ns, int n_pairs, hipStream_t st);
+hipError_t launch_pair_gemm_i8(const PairSlicedArgs& a, int ns, int n_pairs, hipStream_t st);
+// largest n_aux_pad for which the INT8 level sums stay exact with ns digits
+int pair_i8_max_aux_pad(int ns);
 // FP64 rows -> BF16 / FP8 slices, see split.hip
 hipError_t launch_split_rows_bf16(const double* X, long long ldx, int nb, int rows, int rows_pad, int ncols,
                                   int ncols_pad, int ns, __bf16* out, double* norm2, hipStream_t st);
 hipError_t launch_split_rows_fp8(const double* X, long long ldx, int nb, int rows, int rows_pad, int ncols,
                                  int ncols_pad, int ns, uint8_t* out, uint32_t* scales, double* norm2,
                                  hipStream_t st);
+hipError_t launch_split_rows_i8(const double* X, long long ldx, int nb, int rows, int rows_pad, int ncols,
+                                int ncols_pad, int ns, int8_t* out, int* rexp, double* norm2, hipStream_t st);
 
 // ------------------------------------------------------------- density kernel
 struct DensityKernelArgs {

@@ -159,4 +159,75 @@ hipError_t launch_split_rows_fp8(const double* X, long long ldx, int nb, int row
   return hipGetLastError();
 }
 
+
+// ------------------------------------------------------------------ INT8 digits
+// Integer slicing for the INT8 MFMA path: every row x (largest magnitude
+// m = f 2^E, f in [1/2, 1)) is rounded once to the integer
+//     Z = rint(x 2^(6 + 8 (ns-1) - E))          (|Z| <= 2^(6 + 8 (ns-1)))
+// and Z is written in balanced base 256: Z = sum_t d_t 256^(ns-1-t) with
+// d_t in [-128, 127] for t >= 1 and |d_0| <= 64 (the carries of the lower digits
+// add at most 1/2 to the top one).  So x = 2^(E - 6) sum_t d_t 2^(-8t) up to
+// 2^(E - 7 - 8(ns-1)), and products of two rows' digits are exact integers: the
+// pair kernel sums them in INT32 (pair_i8.hip) and applies the row scales
+// 2^(E_a - 6) 2^(E_b - 6) once, in FP64.  Unlike BF16 slices, digits have no
+// exponent of their own, so no row is too small to split.
+//
+// Layout (chunk-major, for the pair kernel's direct loads):
+//   out:  [nb][ncols_pad/32][rows_pad][ns][32] bytes: one 32-wide contraction chunk
+//         of 64 consecutive rows is 64 x 32 ns contiguous bytes
+//   rexp: [nb][rows_pad] the row exponent E - 6 (0 for zero and padding rows)
+// One wave per row; lane l handles four consecutive columns per 256-wide stretch.
+__global__ __launch_bounds__(256) void split_rows_i8_kernel(const double* X, long long ldx, int rows, int rows_pad,
+                                                            int ncols, int ncols_pad, int ns, int8_t* out, int* rexp,
+                                                            double* norm2) {
+  const int lane = threadIdx.x & 63;
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int b = blockIdx.y;
+  if (row >= rows_pad) return;
+  const int nch = ncols_pad >> 5;
+  const double* x = X + ((size_t)b * rows + (row < rows ? row : 0)) * ldx;
+  double m = 0.0, q = 0.0;
+  if (row < rows) {
+    for (int c = lane; c < ncols; c += 64) {
+      m = fmax(m, fabs(x[c]));
+      q += x[c] * x[c];
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
+  q = wave_sum(q);
+  int E = 0;
+  if (m > 0.0) frexp(m, &E);
+  if (lane == 0) {
+    if (norm2 && row < rows) norm2[(size_t)b * rows + row] = q;
+    rexp[(size_t)b * rows_pad + row] = m > 0.0 ? E - 6 : 0;
+  }
+  const int sh = 6 + 8 * (ns - 1) - E;
+  for (int c0 = 4 * lane; c0 < ncols_pad; c0 += 256) {
+    uint32_t word[8];  // ns <= 8
+    for (int t = 0; t < ns; ++t) word[t] = 0u;
+    for (int e = 0; e < 4; ++e) {
+      const int c = c0 + e;
+      long long Z = (row < rows && c < ncols && m > 0.0) ? (long long)rint(ldexp(x[c], sh)) : 0;
+      for (int t = ns - 1; t >= 1; --t) {
+        const long long d = ((Z + 128) & 255) - 128;
+        Z = (Z - d) >> 8;
+        word[t] |= ((uint32_t)d & 0xffu) << (8 * e);
+      }
+      word[0] |= ((uint32_t)Z & 0xffu) << (8 * e);
+    }
+    const int ch = c0 >> 5, kk = c0 & 31;
+    int8_t* dst = out + (((size_t)b * nch + ch) * rows_pad + row) * (size_t)(32 * ns) + kk;
+    for (int t = 0; t < ns; ++t) *reinterpret_cast<uint32_t*>(dst + 32 * t) = word[t];
+  }
+}
+
+hipError_t launch_split_rows_i8(const double* X, long long ldx, int nb, int rows, int rows_pad, int ncols,
+                                int ncols_pad, int ns, int8_t* out, int* rexp, double* norm2, hipStream_t st) {
+  if (rows_pad <= 0 || nb <= 0) return hipSuccess;
+  if (ncols_pad % 32 != 0 || ns < 1 || ns > 8) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(split_rows_i8_kernel, dim3((rows_pad + 3) / 4, nb), dim3(256), 0, st, X, ldx, rows, rows_pad,
+                     ncols, ncols_pad, ns, out, rexp, norm2);
+  return hipGetLastError();
+}
+
 }  // namespace dfpt2

@@ -50,13 +50,21 @@ def test_workspace_sizes(lib):
     b_fp64_d = dp.workspace_size(dp.make_opts(80, 0, 1200, 4000, 0.5, precision=1, slices_gemm2=1))
     b_bf16_d = dp.workspace_size(dp.make_opts(80, 0, 1200, 4000, 0.5, precision=1))
     assert b_bf16_d - b_fp64_d >= 4 * 4 * 2 * 512 * 1216 * 1216
+    # INT8 digits: 5 bytes per element of B instead of 8 for four BF16 slices
+    b_i8 = dp.workspace_size(dp.make_opts(80, 0, 1200, 4000, 0.5, precision=3))
+    assert b_bf16_d - b_i8 >= 3 * 80 * 1216 * 4000 - 80 * 1216 * 4
+    # the exactness limit of the INT8 level sums: n_aux_pad * 5 * 2^14 < 2^31
+    assert dp.workspace_size(dp.make_opts(10, 0, 60, 26208, 0.5, precision=3)) > 0
+    assert dp.workspace_size(dp.make_opts(10, 0, 60, 20000, 0.5, precision=3, slices_gemm1=4)) > 0
 
 
 @pytest.mark.parametrize("bad", [dict(s=0.0), dict(s=-1.0), dict(s=float("nan")), dict(n_vir=0),
                                  dict(n_aux=0), dict(n_core=0, n_act=0), dict(n_core=-1),
                                  dict(precision=7), dict(density_convention=3), dict(slices_gemm1=9),
                                  dict(pair_batch=-5), dict(slices_gemm2=3), dict(precision=1, slices_gemm2=5),
-                                 dict(precision=1, slices_gemm1=5), dict(precision=2, slices_gemm2=2)])
+                                 dict(precision=1, slices_gemm1=5), dict(precision=2, slices_gemm2=2),
+                                 dict(precision=3, slices_gemm1=2), dict(precision=3, slices_gemm1=6),
+                                 dict(precision=3, slices_gemm2=5), dict(precision=3, n_aux=26209)])
 def test_invalid_options_rejected(lib, bad):
     kw = dict(n_core=10, n_act=0, n_vir=60, n_aux=200, s=0.5)
     kw.update({k: v for k, v in bad.items() if k in kw})
