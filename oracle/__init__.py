@@ -14,5 +14,7 @@ Modules:
              pair screen (which is not part of the paper's method)
   naf        natural auxiliary functions (compression of the auxiliary basis
              proposed in the paper's conclusions)
+  ladder     the density-fitted particle-particle ladder of the high-level step
+             (Eq. 6), in the full or the truncated virtual space
 """
-from . import dsrg_pt2, naf, screening  # noqa: F401
+from . import dsrg_pt2, ladder, naf, screening  # noqa: F401

@@ -37,6 +37,14 @@ this order:
   span only an r-dimensional space up to noise, the situation of a large
   automatically generated auxiliary set that natural auxiliary functions compress.
 
+Particle-particle ladder inputs (``ladder_inputs``, a separate stream
+``default_rng(seed)``): virtual energies U[0.1, 5.0] sorted; Z ~ N(0,1) with
+C-order shape (n_aux, n_v, n_v); W ~ N(0,1) with shape (n_amp, n_v, n_v);
+  B^Q_ac = sqrt(d_a d_c) (Z^Q_ac + Z^Q_ca) / sqrt(2)   (symmetric in a, c, as
+           density-fitted virtual-virtual integrals are)
+  T^p_cd = 0.05 W^p_cd / (1 + eps_c + eps_d)          (amplitude-sized matrices)
+with the same decay d_a as above.
+
 Holes are ordered core first, then active.  B is returned in the layout the
 library consumes, ``B[i, a, Q]`` (hole, virtual, auxiliary; auxiliary fastest),
 FP64, C-contiguous.  It is filled chunk by chunk over Q from the same random
@@ -190,3 +198,24 @@ def mlp_init(seed: int = 0, hidden: int = 64, n_in: int = 5) -> np.ndarray:
     W2 = rng.standard_normal((hidden, hidden)) / np.sqrt(hidden)
     w3 = rng.standard_normal(hidden) / np.sqrt(hidden)
     return np.concatenate([W1.ravel(), np.zeros(hidden), W2.ravel(), np.zeros(hidden), w3, [0.0]])
+
+
+@dataclasses.dataclass
+class LadderInputs:
+    eps_vir: np.ndarray      # [n_v]
+    B_vv: np.ndarray         # [n_v, n_v, n_aux], symmetric in the two virtual indices
+    T: np.ndarray            # [n_amp, n_v, n_v]
+    seed: int = 0
+
+
+def ladder_inputs(n_vir: int, n_aux: int, n_amp: int, seed: int = 0) -> LadderInputs:
+    """Draw the particle-particle ladder inputs following the recipe in the module docstring."""
+    rng = np.random.default_rng(seed)
+    eps_vir = np.sort(rng.uniform(0.1, 5.0, n_vir))
+    d = 0.3 / (1.0 + eps_vir) * 0.2
+    z = rng.standard_normal((n_aux, n_vir, n_vir))
+    s = (z + z.transpose(0, 2, 1)) / np.sqrt(2.0)
+    B = np.ascontiguousarray((s * np.sqrt(np.outer(d, d))[None, :, :]).transpose(1, 2, 0))
+    w = rng.standard_normal((n_amp, n_vir, n_vir))
+    T = 0.05 * w / (1.0 + eps_vir[None, :, None] + eps_vir[None, None, :])
+    return LadderInputs(eps_vir=eps_vir, B_vv=B, T=np.ascontiguousarray(T), seed=seed)
