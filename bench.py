@@ -128,6 +128,71 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def ladder_bench(args, wl, cfg):
+    """Particle-particle ladder R^p = sum_cd (ac|bd) T^p_cd at N_V and at N_V' (kept NOs of the
+    workload's FP64 pass at p_o): the (N_V/N_V')^4 saving the truncation is for (Sec. 2, Eq. 6)."""
+    import numpy as np
+    import torch
+    import synth
+    import paper_2312_07008_amd as dp
+
+    s = args.s if args.s is not None else cfg["s"][0]
+    p_o = args.p_o if args.p_o is not None else cfg["p_o"][0]
+    n_core, n_act, n_v, n_aux = cfg["sizes"]
+    inp = synth.generate(n_core, n_act, n_v, n_aux, 0, label=args.workload, **wl["gen"])
+    d = dp.upload_inputs(inp)
+    o64 = dp.make_opts(n_core, n_act, n_v, n_aux, s, precision=dp.FP64)
+    r = dp.build_vv_density(o64, d["eps_hole"], d["eps_vir"], d["gamma_act"], d["B"])
+    t = dp.fno_truncate(r["D_vv"], p_o)
+    k = t["n_kept"]
+    del r, d
+    torch.cuda.empty_cache()
+    n_amp = args.ladder_amps or n_core * n_core
+    t0 = time.time()
+    lin = synth.ladder_inputs(n_v, n_aux, n_amp, seed=0)
+    log(f"ladder inputs n_v={n_v} n_aux={n_aux} n_amp={n_amp} in {time.time() - t0:.1f} s; kept {k} of {n_v}")
+    B = torch.from_numpy(lin.B_vv).cuda()
+    T = torch.from_numpy(lin.T).cuda()
+    del lin
+    stream = torch.cuda.current_stream()
+    out = {}
+    for name, X, m in (("full", None, n_v), ("kept", t["no_vecs"], k)):
+        ws = torch.empty(dp.pp_ladder_workspace_size(n_v, n_aux, n_amp, 0 if X is None else m), dtype=torch.uint8,
+                         device="cuda")
+        R = torch.empty((n_amp, m, m), dtype=torch.float64, device="cuda")
+        for _ in range(args.warmup):
+            dp.pp_ladder(B, T, X, m, R=R, workspace=ws, stream=stream)
+        torch.cuda.synchronize()
+        dp.profile_enable(True)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(args.steps):
+            dp.pp_ladder(B, T, X, m, R=R, workspace=ws, stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        prof = dp.profile_read()
+        dp.profile_enable(False)
+        ms = e0.elapsed_time(e1) / args.steps
+        flops = 2.0 * m ** 4 * (n_aux + n_amp)
+        out[name] = {"n_virtual": m, "ms": ms, "tflops": flops / (ms * 1e-3) / 1e12,
+                     "transform_ms": prof["ladder_transform"][0] / args.steps,
+                     "contraction_ms": prof["ladder"][0] / args.steps}
+        log(f"ladder {name}: N={m} {ms:.1f} ms, {out[name]['tflops']:.1f} TFLOP/s")
+        del ws, R
+        torch.cuda.empty_cache()
+    ratio = out["full"]["ms"] / out["kept"]["ms"]
+    res = {"metric": "particle-particle ladder ms at N_V and at N_V' (FNO)", "value": ratio,
+           "unit": "x (full / kept time)", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "higher_is_better": True, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"{args.workload} sizes, ladder over {n_amp} amplitude matrices, p_o={p_o}",
+                      "n_vir": n_v, "n_kept": k, "n_aux": n_aux, "n_amp": n_amp},
+           "predicted_ratio": (n_v / k) ** 4, "full": out["full"], "kept": out["kept"],
+           "roofline": {"bound": "mfma", "achieved": out["full"]["tflops"], "peak": PEAK_TFLOPS["f64"],
+                        "unit": "TFLOP/s", "frac": out["full"]["tflops"] / PEAK_TFLOPS["f64"],
+                        "traffic": None, "kernel": "gemm_f64 (ladder integrals + contraction)"}}
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -143,6 +208,12 @@ def main():
     ap.add_argument("--naf-scan", action="store_true",
                     help="after the timed steps: natural auxiliary functions at several relative thresholds, "
                          "the compression time, n_naf, and the pass time and energy on the compressed integrals")
+    ap.add_argument("--ladder", action="store_true",
+                    help="instead of the pass: time the particle-particle ladder (the N_V^4 contraction of the "
+                         "high-level step) in the full virtual space and in the space of the kept NOs of the "
+                         "workload's FP64 pass, and print one JSON line for it")
+    ap.add_argument("--ladder-amps", type=int, default=0,
+                    help="amplitude matrices of the ladder run (default: every ordered core pair)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="run one device-to-device copy of this many MiB before timing (a reference "
                          "kernel of known traffic for hardware-counter runs)")
@@ -160,6 +231,8 @@ def main():
 
     wl = WORKLOADS[args.workload]
     cfg = synth.CONFIGS[wl["base"]]
+    if args.ladder:
+        return ladder_bench(args, wl, cfg)
     s = args.s if args.s is not None else cfg["s"][0]
     p_o = args.p_o if args.p_o is not None else cfg["p_o"][0]
     prec = {"fp64": dp.FP64, "bf16": dp.BF16_SLICED, "fp8": dp.FP8_SLICED, "int8": dp.INT8_SLICED}[args.precision]

@@ -190,6 +190,31 @@ int naf_compress_workspace_size(const dfpt2_opts* opts, size_t* bytes);
 int naf_compress(const dfpt2_opts* opts, const double* B, double eps, double* B_naf, double* sigma,
                  int64_t* n_naf, void* workspace, size_t ws_bytes, dfpt2_stream_t stream);
 
+/*
+ * Density-fitted particle-particle ladder, the N_C^2 N_V^4 part of the two-body
+ * contraction of the high-level step (Eq. 6) whose cost the FNO truncation cuts
+ * by (N_V'/N_V)^4 (Sec. 2):
+ *     R^p_ab = sum_cd (ac|bd) T^p_cd,   (ac|bd) = sum_Q B^Q_ac B^Q_bd,
+ * for n_amp amplitude matrices T^p (one per hole pair), FP64 throughout.  With X
+ * (the kept NOs as columns, e.g. from fno_truncate) the inputs are first
+ * transformed, B'^Q = X^T B^Q X and T'^p = X^T T^p X, and R is the ladder in the
+ * truncated space.
+ *   B_vv   [n_vir][n_vir][n_aux] density-fitted virtual-virtual integrals; must be
+ *          symmetric in the two virtual indices (B^Q_ac = B^Q_ca), as such
+ *          integrals are: the library reads (ac|bd) as (ac|db)
+ *   T      [n_amp][n_vir][n_vir]
+ *   X      [n_vir][ldx] or NULL: the first n_kept columns are the kept NOs (fno_truncate's
+ *          no_vecs with ldx = n_vir); NULL = full space (n_kept = 0 or n_vir, ldx ignored)
+ *   R      [n_amp][m][m] out, m = n_kept with X, else n_vir
+ * Limits: n_vir <= 2048, n_amp <= 65535.  Workspace (pp_ladder_workspace_size,
+ * n_kept = 0 for the full space): one block of (ac|bd) of up to ~4 GB plus the
+ * transformed inputs.  Asynchronous on the stream.
+ * Errors: INVALID_ARG, WORKSPACE, HIP.
+ */
+int pp_ladder_workspace_size(int64_t n_vir, int64_t n_aux, int64_t n_amp, int64_t n_kept, size_t* bytes);
+int pp_ladder(int64_t n_vir, int64_t n_aux, int64_t n_amp, const double* B_vv, const double* T, const double* X,
+              int64_t ldx, int64_t n_kept, double* R, void* workspace, size_t ws_bytes, dfpt2_stream_t stream);
+
 /* Symmetric FP64 eigensolver used by fno_truncate (Eq. 8) and the
  * recanonicalization: A [n*n] symmetric (not modified); w [n] out ascending;
  * Z [n*n] out, column k is the eigenvector of w[k]. */
@@ -293,7 +318,9 @@ enum {
   DFPT2_STAGE_KEPT_PAIR = 7,  /* pair kernel of the kept-space energy */
   DFPT2_STAGE_SCREEN = 8,     /* pair features, MLP, mask compaction */
   DFPT2_STAGE_SPLIT_T = 9,    /* amplitude splitting into BF16 slices for the density */
-  DFPT2_NSTAGE = 10
+  DFPT2_STAGE_LADDER_TRANSFORM = 10, /* particle-particle ladder: inputs to the kept NO basis */
+  DFPT2_STAGE_LADDER = 11,    /* particle-particle ladder: integral and contraction GEMMs */
+  DFPT2_NSTAGE = 12
 };
 int dfpt2_profile_enable(int on);
 int dfpt2_profile_read(double* ms, int64_t* launches);

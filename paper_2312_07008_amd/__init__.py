@@ -11,6 +11,7 @@ from .api import (pairscreen_adam_step, pairscreen_build_mask, pairscreen_featur
                   pairscreen_train)
 from .api import (build_vv_density, eigh_sym, fno_truncate, fno_truncate_rule, naf_compress,  # noqa: F401
                   fno_truncate_workspace_size,
-                  make_opts, profile_enable, profile_read, pt2_correction_workspace_size,
+                  make_opts, pp_ladder, pp_ladder_workspace_size, profile_enable, profile_read,
+                  pt2_correction_workspace_size,
                   pt2_energy_correction, upload_inputs,
                   workspace_size)

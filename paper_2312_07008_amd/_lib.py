@@ -63,6 +63,8 @@ SIGNATURES = {
     "fno_truncate_rule": (_int, [_vp, _i64, _int, _dbl, _dbl, _vp, _vp, ctypes.POINTER(_i64),
                                  ctypes.POINTER(_dbl), _vp, _sz, _vp]),
     "dfpt2_eigh_sym": (_int, [_vp, _i64, _vp, _vp, _vp, _sz, _vp]),
+    "pp_ladder_workspace_size": (_int, [_i64, _i64, _i64, _i64, ctypes.POINTER(_sz)]),
+    "pp_ladder": (_int, [_i64, _i64, _i64, _vp, _vp, _vp, _i64, _i64, _vp, _vp, _sz, _vp]),
     "naf_compress_workspace_size": (_int, [ctypes.POINTER(Opts), ctypes.POINTER(_sz)]),
     "naf_compress": (_int, [ctypes.POINTER(Opts), _vp, _dbl, _vp, _vp, ctypes.POINTER(_i64), _vp, _sz, _vp]),
     "pt2_correction_workspace_size": (_int, [ctypes.POINTER(Opts), _i64, ctypes.POINTER(_sz)]),
@@ -85,7 +87,8 @@ SIGNATURES = {
     "dfpt2_profile_read": (_int, [ctypes.POINTER(_dbl), ctypes.POINTER(_i64)]),
 }
 
-STAGES = ["pair", "density", "split", "reduce", "active", "eigh", "transform", "kept_pair", "screen", "split_t"]
+STAGES = ["pair", "density", "split", "reduce", "active", "eigh", "transform", "kept_pair", "screen", "split_t",
+          "ladder_transform", "ladder"]
 
 _lib = None
 

@@ -17,7 +17,7 @@ from ._lib import Opts, check
 
 __all__ = ["make_opts", "workspace_size", "build_vv_density", "fno_truncate_workspace_size",
            "fno_truncate", "fno_truncate_rule", "naf_compress", "eigh_sym", "pt2_correction_workspace_size", "pt2_energy_correction",
-           "upload_inputs", "profile_enable", "profile_read", "pairscreen_num_params", "pairscreen_features",
+           "upload_inputs", "profile_enable", "profile_read", "pp_ladder", "pp_ladder_workspace_size", "pairscreen_num_params", "pairscreen_features",
            "pairscreen_mlp_forward", "pairscreen_mlp_backward", "pairscreen_adam_step", "pairscreen_train",
            "pairscreen_targets", "pairscreen_build_mask"]
 
@@ -176,6 +176,41 @@ def naf_compress(opts, B: torch.Tensor, eps: float, *, workspace=None, stream=No
                            _ptr(ws), ctypes.c_size_t(ws.numel()), _stream(stream)))
     k = int(k.value)
     return dict(B_naf=out[: n_h * n_v * k].view(n_h, n_v, k), sigma=sigma, n_naf=k)
+
+
+def pp_ladder_workspace_size(n_vir: int, n_aux: int, n_amp: int, n_kept: int = 0) -> int:
+    lib = _lib.load()
+    n = ctypes.c_size_t(0)
+    check(lib.pp_ladder_workspace_size(n_vir, n_aux, n_amp, n_kept, ctypes.byref(n)))
+    return int(n.value)
+
+
+def pp_ladder(B_vv: torch.Tensor, T: torch.Tensor, X: Optional[torch.Tensor] = None, n_kept: int = 0, *,
+              R: Optional[torch.Tensor] = None, workspace=None, stream=None) -> torch.Tensor:
+    """Particle-particle ladder R^p_ab = sum_cd (ac|bd) T^p_cd; with X [n_vir, ldx] (its first
+    n_kept columns are the kept NOs, e.g. fno_truncate's no_vecs) in the truncated space.
+    Returns R [n_amp, m, m]."""
+    lib = _lib.load()
+    n_v, n_aux = B_vv.shape[0], B_vv.shape[2]
+    n_amp = T.shape[0]
+    _need(B_vv, "B_vv", torch.float64, n_v * n_v * n_aux)
+    _need(T, "T", torch.float64, n_amp * n_v * n_v)
+    if X is not None:
+        if n_kept < 1:
+            raise ValueError("n_kept must be given with X")
+        if X.dim() != 2 or X.shape[0] != n_v or X.shape[1] < n_kept:
+            raise ValueError("X must be [n_vir, ldx] with ldx >= n_kept")
+        _need(X, "X", torch.float64, X.numel())
+        ldx, m = X.shape[1], n_kept
+    else:
+        n_kept, m, ldx = 0, n_v, 0
+    if R is None:
+        R = torch.empty((n_amp, m, m), dtype=torch.float64, device=B_vv.device)
+    _need(R, "R", torch.float64, n_amp * m * m)
+    ws = _workspace(pp_ladder_workspace_size(n_v, n_aux, n_amp, n_kept), B_vv.device, workspace)
+    check(lib.pp_ladder(n_v, n_aux, n_amp, _ptr(B_vv), _ptr(T), _ptr(X), ldx, n_kept, _ptr(R), _ptr(ws),
+                        ctypes.c_size_t(ws.numel()), _stream(stream)))
+    return R
 
 
 def eigh_sym(A: torch.Tensor, *, workspace=None, stream=None):

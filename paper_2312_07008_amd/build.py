@@ -27,6 +27,7 @@ SOURCES = [
     "fno.hip",
     "correction.cpp",
     "naf.cpp",
+    "ladder.cpp",
     "split.hip",
     "pair_bf16.hip",
     "pair_fp8.hip",

@@ -135,3 +135,26 @@ def test_naf_arguments_rejected(lib):
                             None) == _lib.ERR_INVALID_ARG
     assert lib.naf_compress(ctypes.byref(o), buf, 0.0, buf, buf, ctypes.byref(k), buf, 0,
                             None) == _lib.ERR_WORKSPACE
+
+
+def test_ladder_arguments_rejected(lib):
+    n = ctypes.c_size_t(0)
+    assert lib.pp_ladder_workspace_size(0, 10, 2, 0, ctypes.byref(n)) == _lib.ERR_INVALID_ARG
+    assert lib.pp_ladder_workspace_size(10, 10, 0, 0, ctypes.byref(n)) == _lib.ERR_INVALID_ARG
+    assert lib.pp_ladder_workspace_size(10, 10, 2, 11, ctypes.byref(n)) == _lib.ERR_INVALID_ARG
+    assert lib.pp_ladder_workspace_size(4096, 10, 2, 0, ctypes.byref(n)) == _lib.ERR_INVALID_ARG
+    assert lib.pp_ladder_workspace_size(10, 10, 2, 0, ctypes.byref(n)) == 0 and n.value > 0
+    full = n.value
+    assert lib.pp_ladder_workspace_size(10, 10, 2, 6, ctypes.byref(n)) == 0 and n.value > 0
+    assert full > 0
+    # without X, n_kept other than 0 or n_vir is refused before any device access
+    fake = ctypes.c_void_p(0x1000)
+    st = lib.pp_ladder(10, 10, 2, fake, fake, None, 0, 5, fake, fake, ctypes.c_size_t(1 << 30), None)
+    assert st == _lib.ERR_INVALID_ARG
+    st = lib.pp_ladder(10, 10, 2, None, fake, None, 0, 0, fake, fake, ctypes.c_size_t(1 << 30), None)
+    assert st == _lib.ERR_INVALID_ARG
+    st = lib.pp_ladder(10, 10, 2, fake, fake, None, 0, 0, fake, fake, ctypes.c_size_t(16), None)
+    assert st == _lib.ERR_WORKSPACE
+    # X with a leading dimension below n_kept
+    st = lib.pp_ladder(10, 10, 2, fake, fake, fake, 4, 6, fake, fake, ctypes.c_size_t(1 << 30), None)
+    assert st == _lib.ERR_INVALID_ARG
