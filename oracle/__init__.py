@@ -16,5 +16,7 @@ Modules:
              proposed in the paper's conclusions)
   ladder     the density-fitted particle-particle ladder of the high-level step
              (Eq. 6), in the full or the truncated virtual space
+  a9_active  the Eq. A9 terms whose amplitudes carry an active particle index
+             (zero cumulants, no singles)
 """
-from . import dsrg_pt2, ladder, naf, screening  # noqa: F401
+from . import a9_active, dsrg_pt2, ladder, naf, screening  # noqa: F401

@@ -37,6 +37,13 @@ this order:
   span only an r-dimensional space up to noise, the situation of a large
   automatically generated auxiliary set that natural auxiliary functions compress.
 
+Active-particle integrals (``active_particles=True``, drawn after everything
+above from the same stream): Z' ~ N(0,1) with C-order shape (n_aux, n_h, n_act),
+B_act^Q_ix = d_x Z'^Q_ix with the decay d_x of the active orbital energies, then
+the active-hole / active-particle block symmetrized, B^Q_{n_c+u, x} and
+B^Q_{n_c+x, u} both replaced by their sum over sqrt(2) (B^Q_ux = B^Q_xu, as
+density-fitted integrals are).
+
 Particle-particle ladder inputs (``ladder_inputs``, a separate stream
 ``default_rng(seed)``): virtual energies U[0.1, 5.0] sorted; Z ~ N(0,1) with
 C-order shape (n_aux, n_v, n_v); W ~ N(0,1) with shape (n_amp, n_v, n_v);
@@ -69,6 +76,7 @@ class Inputs:
     B: np.ndarray                 # [n_h, n_vir, n_aux]
     seed: int = 0
     label: str = ""
+    B_act: Optional[np.ndarray] = None  # [n_h, n_act, n_aux] hole / active-particle integrals, or None
 
     @property
     def n_core(self) -> int:
@@ -106,7 +114,7 @@ def _haar_orthogonal(rng: np.random.Generator, n: int) -> np.ndarray:
 
 def generate(n_core: int, n_act: int, n_vir: int, n_aux: int, seed: int = 0, *,
              low_rank: int = 0, localized_xi: Optional[float] = None,
-             aux_rank: int = 0, aux_noise: float = 0.0,
+             aux_rank: int = 0, aux_noise: float = 0.0, active_particles: bool = False,
              q_chunk: int = 256, label: str = "") -> Inputs:
     """Draw one input set following the recipe in the module docstring."""
     if n_act % 2:
@@ -153,8 +161,15 @@ def generate(n_core: int, n_act: int, n_vir: int, n_aux: int, seed: int = 0, *,
         xh = rng.uniform(0.0, 40.0, n_h)
         yq = rng.uniform(0.0, 40.0, n_aux)
         B *= np.exp(-np.abs(xh[:, None] - yq[None, :]) / localized_xi)[:, None, :]
+    B_act = None
+    if active_particles and n_act:
+        z = rng.standard_normal((n_aux, n_h, n_act))
+        dx = 0.3 / (1.0 + eps_act) * 0.2
+        B_act = np.ascontiguousarray(z.transpose(1, 2, 0) * dx[None, :, None])
+        blk = B_act[n_core:].copy()
+        B_act[n_core:] = (blk + blk.transpose(1, 0, 2)) / np.sqrt(2.0)
     return Inputs(eps_core=eps_core, eps_act=eps_act, eps_vir=eps_vir,
-                  gamma_act=gamma, B=B, seed=seed, label=label)
+                  gamma_act=gamma, B=B, seed=seed, label=label, B_act=B_act)
 
 
 # Workload presets.  Sizes are (n_core, n_act, n_vir, n_aux).

@@ -13,6 +13,11 @@ with antisymmetrized spin-orbital integrals, A = T - T^+, and then evaluates
         (App. A, Eq. A4: the scalar part of the second-order Hamiltonian)
 as plain matrix traces.  For a quasi-free rho every normal-ordered remainder has
 zero expectation, so the traces are the fully contracted scalars of the paper.
+
+With ``B_act`` (integrals B^Q_ix of hole i and active particle x) the particle
+indices of the doubles run over active and virtual orbitals, as in the
+multireference theory (holes: core and active; particles: active and virtual;
+excitations with four active indices are internal and left out).
 """
 from __future__ import annotations
 
@@ -43,10 +48,11 @@ def _occupation_probabilities(n_modes, probs):
     return diag
 
 
-def brute_force_pt2(eps_core, eps_act, eps_vir, gamma_act, B, s):
+def brute_force_pt2(eps_core, eps_act, eps_vir, gamma_act, B, s, B_act=None):
     """Return (E2, Gamma_vv) by explicit Fock-space traces.
 
-    Spatial orbitals: core, active, virtual.  Spin orbital index 2 p + sigma."""
+    Spatial orbitals: core, active, virtual.  Spin orbital index 2 p + sigma.
+    B_act [n_h, n_act, n_aux]: with it, active particle indices are included."""
     n_c, n_a, n_v = len(eps_core), len(eps_act), len(eps_vir)
     n_h = n_c + n_a
     n_sp = n_h + n_v
@@ -86,6 +92,11 @@ def brute_force_pt2(eps_core, eps_act, eps_vir, gamma_act, B, s):
 
     holes = [(i, sig) for i in range(n_h) for sig in range(2)]
     virts = [(n_h + a_, sig) for a_ in range(n_v) for sig in range(2)]
+    if B_act is not None:
+        # particles: active then virtual; B_all[i, p] over particle orbitals p
+        virts = [(n_c + x_, sig) for x_ in range(n_a) for sig in range(2)] + virts
+        B_all = np.concatenate([B_act, B], axis=1)
+        Vall = np.einsum("ipQ,jqQ->ijpq", B_all, B_all)
 
     def so(p):
         return 2 * p[0] + p[1]
@@ -94,7 +105,34 @@ def brute_force_pt2(eps_core, eps_act, eps_vir, gamma_act, B, s):
         """<AB|IJ> in spin orbitals (physicists' notation; spin-free part (ai|bj))."""
         if A_[1] != I_[1] or B_[1] != J_[1]:
             return 0.0
-        return Vsp[I_[0], J_[0], A_[0] - n_h, B_[0] - n_h]
+        if B_act is None:
+            return Vsp[I_[0], J_[0], A_[0] - n_h, B_[0] - n_h]
+        return Vall[I_[0], J_[0], A_[0] - n_c, B_[0] - n_c]
+
+    def internal(*idx):
+        return all(n_c <= q[0] < n_h for q in idx)
+
+    # one-body contractions c(p, q) = Tr(rho a+_p a_q) of the reference, for the
+    # normal-ordered excitation operators of the cluster operator
+    cmat = {}
+
+    def cval(p, q):
+        key = (so(p), so(q))
+        if key not in cmat:
+            cmat[key] = tr(ad[key[0]] @ a[key[1]])
+        return cmat[key]
+
+    def excitation(A_, B_, I_, J_):
+        """{a+_A a+_B a_J a_I}: normal ordered with respect to the (quasi-free)
+        reference, i.e. the bare product minus its contractions (Wick)."""
+        ex = ad[so(A_)] @ ad[so(B_)] @ a[so(J_)] @ a[so(I_)]
+        cAI, cAJ, cBI, cBJ = cval(A_, I_), cval(A_, J_), cval(B_, I_), cval(B_, J_)
+        if cAI or cAJ or cBI or cBJ:
+            one = sp.identity(ex.shape[0], format="csr")
+            ex = (ex - cAI * (ad[so(B_)] @ a[so(J_)]) + cAJ * (ad[so(B_)] @ a[so(I_)])
+                  - cBJ * (ad[so(A_)] @ a[so(I_)]) + cBI * (ad[so(A_)] @ a[so(J_)])
+                  + (cAI * cBJ - cAJ * cBI) * one)
+        return ex.tocsr()
 
     T = None
     Vop = None
@@ -104,12 +142,14 @@ def brute_force_pt2(eps_core, eps_act, eps_vir, gamma_act, B, s):
             for p in range(len(virts)):
                 for q in range(p + 1, len(virts)):
                     A_, B_ = virts[p], virts[q]
+                    if internal(I_, J_, A_, B_):
+                        continue
                     v = g(A_, B_, I_, J_) - g(A_, B_, J_, I_)
                     if v == 0.0:
                         continue
                     dl = eps[I_[0]] + eps[J_[0]] - eps[A_[0]] - eps[B_[0]]
                     t = v * (1.0 - np.exp(-s * dl * dl)) / dl
-                    ex = ad[so(A_)] @ ad[so(B_)] @ a[so(J_)] @ a[so(I_)]
+                    ex = excitation(A_, B_, I_, J_)
                     T = t * ex if T is None else T + t * ex
                     Vop = v * ex if Vop is None else Vop + v * ex
     Aop = (T - T.T).tocsr()
