@@ -168,6 +168,29 @@ int fno_truncate_rule(const double* D_vv, int64_t n_vir, int rule, double param,
                       double* occ, double* no_vecs, int64_t* n_kept, double* margins,
                       void* workspace, size_t ws_bytes, dfpt2_stream_t stream);
 
+/* Workspace (bytes) for dfpt2_add_active_particle_density.  bytes: host out. */
+int dfpt2_active_particle_workspace_size(const dfpt2_opts* opts, size_t* bytes);
+
+/*
+ * Adds to D_vv the Eq. A9 terms whose amplitudes carry one virtual and one active
+ * particle index (the multireference amplitudes t^{ex}_{ij} of Eq. A7 with x active),
+ * at zero density cumulants and without singles:
+ *     t^{ev}_{mn} tc^{fu}_{mn} eta^u_v + 1/2 S(t^{ey}_{mu} tc^{fx}_{mv}) Gamma^u_v eta^x_y
+ *   + 1/4 t^{ez}_{ux} tc^{fw}_{vy} Gamma^u_v Gamma^x_y eta^w_z,      eta = 2 - Gamma_act
+ * (the active-active term with the exchange combination tc on its second amplitude).
+ *   opts       as for dfpt2_build_vv_density (s, sizes, density_convention)
+ *   eps_hole   [n_core + n_act] (the active energies are those of the active particles too)
+ *   eps_vir, gamma_act, B   as for dfpt2_build_vv_density
+ *   B_act      [n_h][n_act][n_aux] density-fitted integrals B^Q_ix of hole i and active
+ *              particle x (symmetric in the active-active block, as such integrals are)
+ *   D_vv       [n_vir][n_vir] in/out: the terms are added, symmetrized
+ * Does nothing when n_act = 0.  FP64 throughout.  Asynchronous on the stream.
+ * Errors: INVALID_ARG, WORKSPACE, HIP.
+ */
+int dfpt2_add_active_particle_density(const dfpt2_opts* opts, const double* eps_hole, const double* eps_vir,
+                                      const double* gamma_act, const double* B, const double* B_act, double* D_vv,
+                                      void* workspace, size_t ws_bytes, dfpt2_stream_t stream);
+
 /* Workspace (bytes) for naf_compress (sizes from opts).  bytes: host out. */
 int naf_compress_workspace_size(const dfpt2_opts* opts, size_t* bytes);
 

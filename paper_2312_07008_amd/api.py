@@ -17,7 +17,8 @@ from ._lib import Opts, check
 
 __all__ = ["make_opts", "workspace_size", "build_vv_density", "fno_truncate_workspace_size",
            "fno_truncate", "fno_truncate_rule", "naf_compress", "eigh_sym", "pt2_correction_workspace_size", "pt2_energy_correction",
-           "upload_inputs", "profile_enable", "profile_read", "pp_ladder", "pp_ladder_workspace_size", "pairscreen_num_params", "pairscreen_features",
+           "upload_inputs", "profile_enable", "profile_read", "pp_ladder", "pp_ladder_workspace_size",
+           "add_active_particle_density", "pairscreen_num_params", "pairscreen_features",
            "pairscreen_mlp_forward", "pairscreen_mlp_backward", "pairscreen_adam_step", "pairscreen_train",
            "pairscreen_targets", "pairscreen_build_mask"]
 
@@ -178,6 +179,26 @@ def naf_compress(opts, B: torch.Tensor, eps: float, *, workspace=None, stream=No
     return dict(B_naf=out[: n_h * n_v * k].view(n_h, n_v, k), sigma=sigma, n_naf=k)
 
 
+def add_active_particle_density(opts: Opts, eps_hole, eps_vir, gamma_act, B, B_act, D_vv, *, workspace=None,
+                                stream=None) -> torch.Tensor:
+    """D_vv += the Eq. A9 terms with an active particle index (zero cumulants); returns D_vv."""
+    lib = _lib.load()
+    n_h, n_v, n_a, n_aux = opts.n_core + opts.n_act, opts.n_vir, opts.n_act, opts.n_aux
+    _need(eps_hole, "eps_hole", torch.float64, n_h)
+    _need(eps_vir, "eps_vir", torch.float64, n_v)
+    _need(gamma_act, "gamma_act", torch.float64, n_a * n_a)
+    _need(B, "B", torch.float64, n_h * n_v * n_aux)
+    _need(B_act, "B_act", torch.float64, n_h * n_a * n_aux)
+    _need(D_vv, "D_vv", torch.float64, n_v * n_v)
+    n = ctypes.c_size_t(0)
+    check(lib.dfpt2_active_particle_workspace_size(ctypes.byref(opts), ctypes.byref(n)))
+    ws = _workspace(int(n.value), D_vv.device, workspace)
+    check(lib.dfpt2_add_active_particle_density(ctypes.byref(opts), _ptr(eps_hole), _ptr(eps_vir), _ptr(gamma_act),
+                                                _ptr(B), _ptr(B_act), _ptr(D_vv), _ptr(ws),
+                                                ctypes.c_size_t(ws.numel()), _stream(stream)))
+    return D_vv
+
+
 def pp_ladder_workspace_size(n_vir: int, n_aux: int, n_amp: int, n_kept: int = 0) -> int:
     lib = _lib.load()
     n = ctypes.c_size_t(0)
@@ -262,6 +283,8 @@ def upload_inputs(inp, device="cuda") -> dict:
         return torch.from_numpy(x).to(device=device, dtype=torch.float64).contiguous()
     out = dict(eps_hole=t(inp.eps_hole), eps_vir=t(inp.eps_vir), B=t(inp.B))
     out["gamma_act"] = t(inp.gamma_act.reshape(-1)) if inp.n_act else None
+    if getattr(inp, "B_act", None) is not None:
+        out["B_act"] = t(inp.B_act)
     return out
 
 

@@ -28,6 +28,7 @@ SOURCES = [
     "correction.cpp",
     "naf.cpp",
     "ladder.cpp",
+    "active_particle.hip",
     "split.hip",
     "pair_bf16.hip",
     "pair_fp8.hip",

@@ -158,3 +158,18 @@ def test_ladder_arguments_rejected(lib):
     # X with a leading dimension below n_kept
     st = lib.pp_ladder(10, 10, 2, fake, fake, fake, 4, 6, fake, fake, ctypes.c_size_t(1 << 30), None)
     assert st == _lib.ERR_INVALID_ARG
+
+
+def test_active_particle_arguments_rejected(lib):
+    o = dp.make_opts(4, 2, 30, 20, 0.5)
+    n = ctypes.c_size_t(0)
+    assert lib.dfpt2_active_particle_workspace_size(ctypes.byref(o), ctypes.byref(n)) == 0 and n.value > 0
+    fake = ctypes.c_void_p(0x1000)
+    st = lib.dfpt2_add_active_particle_density(ctypes.byref(o), fake, fake, fake, fake, None, fake, fake,
+                                               ctypes.c_size_t(n.value), None)
+    assert st == _lib.ERR_INVALID_ARG
+    st = lib.dfpt2_add_active_particle_density(ctypes.byref(o), fake, fake, fake, fake, fake, fake, fake,
+                                               ctypes.c_size_t(16), None)
+    assert st == _lib.ERR_WORKSPACE
+    bad = dp.make_opts(4, 2, 30, 20, -1.0)
+    assert lib.dfpt2_active_particle_workspace_size(ctypes.byref(bad), ctypes.byref(n)) == _lib.ERR_INVALID_ARG
