@@ -230,7 +230,7 @@ int naf_compress(const dfpt2_opts* opts, const double* B, double eps, double* B_
  *          no_vecs with ldx = n_vir); NULL = full space (n_kept = 0 or n_vir, ldx ignored)
  *   R      [n_amp][m][m] out, m = n_kept with X, else n_vir
  * Limits: n_vir <= 2048, n_amp <= 65535.  Workspace (pp_ladder_workspace_size,
- * n_kept = 0 for the full space): one block of (ac|bd) of up to ~4 GB plus the
+ * n_kept = 0 for the full space): one block of (ac|bd) of up to ~16 GB plus the
  * transformed inputs.  Asynchronous on the stream.
  * Errors: INVALID_ARG, WORKSPACE, HIP.
  */

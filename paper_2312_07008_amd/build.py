@@ -25,6 +25,7 @@ SOURCES = [
     "util.hip",
     "eigh.hip",
     "fno.hip",
+    "gemm_f64.hip",
     "correction.cpp",
     "naf.cpp",
     "ladder.cpp",

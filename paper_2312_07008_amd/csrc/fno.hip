@@ -71,101 +71,8 @@ __global__ void rule_threshold_kernel(const double* occ, int n, int rule, double
   *flag = bad;
 }
 
-// ------------------------------------------------------------- batched GEMM
-// C[b] = alpha * op(A[b]) op(B[b]) (+ beta C[b]); op(A) is M x K, op(B) is K x N.
-struct GemmArgs {
-  const double* A;
-  const double* B;
-  double* C;
-  int M, N, K;
-  int lda, ldb, ldc;
-  long long sA, sB, sC;
-  int transA, transB;
-  double alpha, beta;
-};
-
-constexpr int GT = 64, GK = 16;
-
-__global__ __launch_bounds__(256) void gemm_f64_kernel(GemmArgs g) {
-  __shared__ double As[GT][GK + 1];
-  __shared__ double Bs[GK][GT + 1];
-  const int b = blockIdx.z;
-  const int m0 = blockIdx.y * GT, n0 = blockIdx.x * GT;
-  const double* A = g.A + b * g.sA;
-  const double* Bm = g.B + b * g.sB;
-  double* C = g.C + b * g.sC;
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int wr = w >> 1, wc = w & 1, r16 = lane & 15, kq = lane >> 4;
-  d4 acc[2][2];
-  for (int x = 0; x < 2; ++x)
-    for (int y = 0; y < 2; ++y) acc[x][y] = (d4){0.0, 0.0, 0.0, 0.0};
-  for (int k0 = 0; k0 < g.K; k0 += GK) {
-    for (int e = tid; e < GT * GK; e += 256) {
-      int mm, kk;
-      if (g.transA) {  // A stored K x M: read along m
-        kk = e / GT;
-        mm = e % GT;
-      } else {
-        mm = e / GK;
-        kk = e % GK;
-      }
-      const int gm = m0 + mm, gk = k0 + kk;
-      double v = 0.0;
-      if (gm < g.M && gk < g.K) v = g.transA ? A[(size_t)gk * g.lda + gm] : A[(size_t)gm * g.lda + gk];
-      As[mm][kk] = v;
-    }
-    for (int e = tid; e < GT * GK; e += 256) {
-      int nn, kk;
-      if (g.transB) {  // B stored N x K: read along k
-        nn = e / GK;
-        kk = e % GK;
-      } else {
-        kk = e / GT;
-        nn = e % GT;
-      }
-      const int gn = n0 + nn, gk = k0 + kk;
-      double v = 0.0;
-      if (gn < g.N && gk < g.K) v = g.transB ? Bm[(size_t)gn * g.ldb + gk] : Bm[(size_t)gk * g.ldb + gn];
-      Bs[kk][nn] = v;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int k4 = 0; k4 < GK / 4; ++k4) {
-      const int k = k4 * 4 + kq;
-      const double a0 = As[wr * 32 + r16][k], a1 = As[wr * 32 + 16 + r16][k];
-      const double b0 = Bs[k][wc * 32 + r16], b1 = Bs[k][wc * 32 + 16 + r16];
-      acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
-      acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
-      acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
-      acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
-    }
-    __syncthreads();
-  }
-  for (int bi = 0; bi < 2; ++bi)
-    for (int r = 0; r < 4; ++r) {
-      const int gm = m0 + wr * 32 + bi * 16 + kq + 4 * r;
-      if (gm >= g.M) continue;
-      for (int bj = 0; bj < 2; ++bj) {
-        const int gn = n0 + wc * 32 + bj * 16 + r16;
-        if (gn >= g.N) continue;
-        double* dst = C + (size_t)gm * g.ldc + gn;
-        const double v = g.alpha * acc[bi][bj][r];
-        *dst = (g.beta != 0.0) ? v + g.beta * *dst : v;
-      }
-    }
-}
-
 }  // namespace
 
-hipError_t gemm_f64(const double* A, int lda, long long sA, int transA, const double* B, int ldb, long long sB,
-                    int transB, double* C, int ldc, long long sC, int M, int N, int K, int batch, double alpha,
-                    double beta, hipStream_t st) {
-  if (M <= 0 || N <= 0 || batch <= 0) return hipSuccess;
-  GemmArgs g{A, B, C, M, N, K, lda, ldb, ldc, sA, sB, sC, transA, transB, alpha, beta};
-  dim3 grid((N + GT - 1) / GT, (M + GT - 1) / GT, batch);
-  hipLaunchKernelGGL(gemm_f64_kernel, grid, dim3(256), 0, st, g);
-  return hipGetLastError();
-}
 
 }  // namespace dfpt2
 

@@ -12,7 +12,8 @@
 // (b,d) order of B because density-fitted integrals are symmetric in their two
 // orbital indices (B^Q_db = B^Q_bd); that lays G out as [(c,d)][b] per a, the
 // operand the second product contracts over (c,d).  G of one block holds
-// m_a N^3 doubles (m_a <= 32 values of a, at most ~4 GB, at least one a).
+// m_a N^3 doubles (m_a <= 32 values of a, at most ~16 GB, at least one a): the
+// contraction runs as m_a batched GEMMs of n_amp x N, so m_a sets its parallelism.
 //
 // Truncated space: with the kept NOs X [N_V][ldx] (first N' columns) the inputs are transformed
 // first, B'^Q = X^T B^Q X (over both virtual indices of B[a][c][Q]) and
@@ -34,7 +35,7 @@ struct LadderPlan {
   size_t off_Y, off_Bk, off_Z, off_Tk, off_G, bytes;
 };
 
-constexpr double kGBlockBytes = 4.0e9;
+constexpr double kGBlockBytes = 16.0e9;  // one block of (ac|bd): enough values of a to fill the GPU
 constexpr int kMaxBlockRows = 32;  // values of a per block
 
 int plan_ladder(int64_t n_vir, int64_t n_aux, int64_t n_amp, int64_t n_kept, bool transform, LadderPlan* pl) {
