@@ -201,6 +201,8 @@ def main():
     ap.add_argument("--workload", default="c4", choices=sorted(WORKLOADS))
     ap.add_argument("--precision", default="bf16", choices=["int8", "bf16", "fp8", "fp64"])
     ap.add_argument("--no-screen", action="store_true")
+    ap.add_argument("--slices-gemm2", type=int, default=0,
+                    help="slices (BF16) or digits (INT8) per operand of the density product; 0 = library default")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-ref", action="store_true")
     ap.add_argument("--s", type=float, default=None)
@@ -208,6 +210,8 @@ def main():
     ap.add_argument("--naf-scan", action="store_true",
                     help="after the timed steps: natural auxiliary functions at several relative thresholds, "
                          "the compression time, n_naf, and the pass time and energy on the compressed integrals")
+    ap.add_argument("--no-alt", action="store_true",
+                    help="skip the INT8-digit measurement reported beside a BF16 run")
     ap.add_argument("--ladder", action="store_true",
                     help="instead of the pass: time the particle-particle ladder (the N_V^4 contraction of the "
                          "high-level step) in the full virtual space and in the space of the kept NOs of the "
@@ -245,7 +249,7 @@ def main():
     log(f"inputs {args.workload} {cfg['sizes']} {wl['gen']} generated in {time.time() - t0:.1f} s")
     d = dp.upload_inputs(inp)
     n_h = inp.n_h
-    opts = dp.make_opts(n_core, n_act, n_v, n_aux, s, precision=prec)
+    opts = dp.make_opts(n_core, n_act, n_v, n_aux, s, precision=prec, slices_gemm2=args.slices_gemm2)
     stream = torch.cuda.current_stream()
 
     # ---- untimed setup: train the screen on small plain-pass labels
@@ -406,6 +410,46 @@ def main():
             del nr, rk
             torch.cuda.empty_cache()
         out["naf_scan"] = scan
+    if args.precision == "bf16" and not args.no_alt:
+        # the same screened build with B as INT8 digits (exact INT32 level sums), untimed by the
+        # headline: ms per pass, its pair kernel against the INT8 peak, and its error
+        o8 = dp.make_opts(n_core, n_act, n_v, n_aux, s, precision=dp.INT8_SLICED)
+        ws8 = torch.empty(dp.workspace_size(o8), dtype=torch.uint8, device="cuda")
+        D8 = torch.empty((n_v, n_v), dtype=torch.float64, device="cuda")
+        e8 = torch.empty(2, dtype=torch.float64, device="cuda")
+        times8 = []
+        for it in range(3):
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+            if it == 1:
+                dp.profile_enable(True)
+            ev[0].record(stream)
+            mask8 = None
+            if screen:
+                mask8, _ = screening.predict_mask(W, opts, d["eps_hole"], d["eps_vir"], d["B"], SCREEN_THRESHOLD,
+                                                  margin, stream=stream)
+            dp.build_vv_density(o8, d["eps_hole"], d["eps_vir"], d["gamma_act"], d["B"], mask8, D_vv=D8, e_pt2=e8,
+                                workspace=ws8, stream=stream)
+            ev[1].record(stream)
+            torch.cuda.synchronize()
+            if it >= 1:
+                times8.append(ev[0].elapsed_time(ev[1]))
+        p8 = dp.profile_read()
+        dp.profile_enable(False)
+        t8 = dp.fno_truncate(D8, p_o)
+        E8 = e8.cpu().numpy()
+        pk8_ms, pk8_n = p8["pair"]
+        ach8 = (15 * 2.0 * n_v * n_v * n_aux * computed * 2) / (pk8_ms * 1e-3) / 1e12 if pk8_n else None
+        out["alt_int8"] = {"ms_per_pass": statistics.median(times8), "n_kept": t8["n_kept"],
+                           "pair_kernel_ms_per_launch": pk8_ms / pk8_n if pk8_n else None,
+                           "pair_kernel_TOPs": ach8, "pair_kernel_frac_of_int8_peak": ach8 / PEAK_TFLOPS["i8"]
+                           if ach8 else None, "E_pt2": [float(E8[0]), float(E8[1])]}
+        if ref is not None:
+            out["alt_int8"]["delta_E_vs_fp64_Eh"] = dd((float(E8[0]), float(E8[1])),
+                                                       (float(ref["E"][0]), float(ref["E"][1])))
+            out["alt_int8"]["max_dON_vs_fp64"] = float(np.abs(t8["occ"].cpu().numpy() - ref["occ"]).max())
+        log(f"INT8 digits: {out['alt_int8']['ms_per_pass']:.1f} ms per pass, kept {t8['n_kept']}")
+        del ws8, D8
+        torch.cuda.empty_cache()
     if ref is not None:
         out["fp64_ms_per_pass"] = ref["ms"]
         out["speedup_vs_fp64"] = ref["ms"] / ms_pass

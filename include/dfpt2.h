@@ -62,8 +62,8 @@ typedef enum {
   DFPT2_FP64 = 0,         /* FP64 MFMA for both contractions */
   DFPT2_BF16_SLICED = 1,  /* B and T split into BF16 slices; exact FP32 chunk sums, FP64 across chunks */
   DFPT2_FP8_SLICED = 2,   /* FP8 e4m3 slices with per-block power-of-two scales */
-  DFPT2_INT8_SLICED = 3   /* B as balanced base-256 INT8 digits per row; exact INT32 level sums on the
-                             INT8 MFMA (n_aux <= 26208 at 5 digits); density as with BF16 */
+  DFPT2_INT8_SLICED = 3   /* B and T as balanced base-256 INT8 digits per row; exact INT32 level sums on
+                             the INT8 MFMA (n_aux <= 26208 at 5 digits) */
 } dfpt2_precision;
 
 typedef struct dfpt2_opts {
@@ -76,8 +76,8 @@ typedef struct dfpt2_opts {
   int32_t slices_gemm1;       /* slices per operand of V = B B^T; 0 = precision default
                                (BF16, FP8: 4, range 2..4; INT8: 5 digits, range 3..5) */
   int32_t slices_gemm2;       /* slices per operand of the density product: 0 = precision default
-                               (BF16, INT8: 4; FP64, FP8: FP64 density), 1 = FP64 density, 2..4 = BF16
-                               slices (BF16 and INT8 precision only) */
+                               (BF16: 4 BF16 slices; INT8: 5 INT8 digits; FP64, FP8: FP64 density),
+                               1 = FP64 density, 2..4 BF16 slices (BF16), 2..5 digits (INT8) */
   int32_t density_convention; /* 0: spin-summed Gamma^(2)_vv (Eq. A9); 1: per spin (half) */
   int64_t pair_batch;         /* unordered pairs per batch; 0 = library default */
 } dfpt2_opts;

@@ -36,6 +36,7 @@ SOURCES = [
     "pair_i8.hip",
     "split_t.hip",
     "density_bf16.hip",
+    "density_i8.hip",
     "active.hip",
     "screen.hip",
     "prof.cpp",

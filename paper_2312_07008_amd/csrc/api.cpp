@@ -98,10 +98,13 @@ int plan_pass(const dfpt2_opts* o, PassPlan* pl, bool energy_only) {
                   p.n_aux, p.ns1, pair_i8_max_aux_pad(p.ns1));
   }
   const bool sliced_density = p.precision == DFPT2_BF16_SLICED || p.precision == DFPT2_INT8_SLICED;
-  p.ns2 = o->slices_gemm2 ? o->slices_gemm2 : (sliced_density ? 4 : 1);
-  if (p.ns2 > 4 || (p.ns2 > 1 && !sliced_density))
+  const int ns2_max = p.precision == DFPT2_INT8_SLICED ? 5 : 4;
+  p.ns2 = o->slices_gemm2 ? o->slices_gemm2 : (p.precision == DFPT2_INT8_SLICED ? 5 : sliced_density ? 4 : 1);
+  if (p.ns2 > ns2_max || (p.ns2 > 1 && !sliced_density))
     return fail(DFPT2_ERR_INVALID_ARG,
-                "slices_gemm2 must be 1 (FP64 density) or, with BF16 or INT8 precision, 2..4");
+                "slices_gemm2 must be 1 (FP64 density) or 2..4 BF16 slices (BF16) or 2..5 INT8 digits (INT8)");
+  if (p.precision == DFPT2_INT8_SLICED && p.ns2 >= 2 && (long long)(p.ns2 - 1) * 16384 * p.n_v_pad_d >= 0x7fffffffLL)
+    return fail(DFPT2_ERR_INVALID_ARG, "n_vir too large for exact INT8 density sums with %d digits", p.ns2);
   if (energy_only) p.ns2 = 1;
   // split-BF16 density: splits of the pair range chosen so that tile pairs x splits
   // fill whole rounds of two workgroups per CU on 256 CUs
@@ -143,7 +146,11 @@ int plan_pass(const dfpt2_opts* o, PassPlan* pl, bool energy_only) {
                                                       : 0);
   p.off_norm2 = take(p.precision != DFPT2_FP64 ? sizeof(double) * (size_t)p.n_h * p.n_v : 0);
   p.off_rexp = take(p.precision == DFPT2_INT8_SLICED ? sizeof(int) * (size_t)p.n_h * p.n_v_pad : 0);
-  p.off_Ts = take(p.ns2 >= 2 ? sizeof(__bf16) * 4 * (size_t)p.batch * p.n_v_pad_d * p.n_v_pad_d * p.ns2 : 0);
+  // density operands: BF16 slices, or INT8 digits (+ row exponents) with INT8 precision
+  const size_t t_bytes = p.precision == DFPT2_INT8_SLICED ? 1 : sizeof(__bf16);
+  p.off_Ts = take(p.ns2 >= 2 ? t_bytes * 4 * (size_t)p.batch * p.n_v_pad_d * p.n_v_pad_d * p.ns2 : 0);
+  p.off_Texp = take(p.ns2 >= 2 && p.precision == DFPT2_INT8_SLICED ? sizeof(int) * 4 * (size_t)p.batch * p.n_v_pad_d
+                                                                    : 0);
   p.off_dg = take(p.ns2 >= 2 ? sizeof(double) * (size_t)p.batch * (p.n_v_pad_d / 64) * p.n_v_pad_d : 0);
   p.off_tmax = take(p.ns2 >= 2 ? sizeof(unsigned long long) * 4 * (size_t)p.batch * p.n_v_pad_d : 0);
   p.off_diag = take(p.ns2 >= 2 ? sizeof(double) * (size_t)p.n_v : 0);
@@ -506,6 +513,33 @@ int run_pass(const PassPlan& pl, const dfpt2_opts& o, const double* eps_h, const
         return hip_fail(e, "pair reduce");
     }
     if (pl.energy_only) continue;
+    if (pl.ns2 >= 2 && pl.precision == DFPT2_INT8_SLICED) {
+      int8_t* Ts = reinterpret_cast<int8_t*>(ws + pl.off_Ts);
+      int* Texp = reinterpret_cast<int*>(ws + pl.off_Texp);
+      {
+        ProfScope ps(DFPT2_STAGE_SPLIT_T, s);
+        if ((e = launch_split_t_i8(T, pairs + p0, nullptr, pl.w_density, np, pl.n_v, pl.n_v_pad_d, pl.ns2, pa.tmax,
+                                   pa.dgp, Ts, Texp, reinterpret_cast<double*>(ws + pl.off_diag), s)) != hipSuccess)
+          return hip_fail(e, "amplitude digits");
+      }
+      DensityDigitArgs dd{};
+      dd.Ts = Ts;
+      dd.rexp = Texp;
+      dd.pw = nullptr;
+      dd.pairs = pairs + p0;
+      dd.Dpart = Dpart;
+      dd.n_v = pl.n_v;
+      dd.n_v_pad = pl.n_v_pad_d;
+      dd.nt = pl.nt;
+      dd.nTP = pl.nTP;
+      dd.n_pairs = np;
+      dd.nsplit = pl.nsplit2 < np ? pl.nsplit2 : np;
+      dd.w = pl.w_density;
+      dd.accumulate = 1;
+      ProfScope ps(DFPT2_STAGE_DENSITY, s);
+      if ((e = launch_density_i8(dd, pl.ns2, s)) != hipSuccess) return hip_fail(e, "density kernel (INT8)");
+      continue;
+    }
     if (pl.ns2 >= 2) {
       __bf16* Ts = reinterpret_cast<__bf16*>(ws + pl.off_Ts);
       {

@@ -91,6 +91,22 @@ hipError_t launch_split_t_bf16(const double* T, const int2* pairs, const double*
                                int n_v_pad, int ns, const unsigned long long* tmax, const double* dgp, __bf16* out,
                                double* diag, hipStream_t st);
 hipError_t launch_density_bf16(const DensitySlicedArgs& a, int ns, hipStream_t st);
+
+// INT8-digit density: digits of the four operands (split_t.hip) and the digit product
+struct DensityDigitArgs {
+  const int8_t* Ts;     // [n_pairs][4][n_v_pad/32][n_v_pad][ns][32] (split_t.hip)
+  const int* rexp;      // [n_pairs][4][n_v_pad] row exponents
+  const double* pw;     // [n_pairs] per-pair weight, or null
+  const int2* pairs;    // [n_pairs]
+  double* Dpart;        // [nsplit][n_v][n_v]
+  int n_v, n_v_pad, nt, nTP, n_pairs, nsplit;
+  double w;             // weight of one ordered pair
+  int accumulate;
+};
+hipError_t launch_split_t_i8(const double* T, const int2* pairs, const double* pw, double w, int n_pairs, int n_v,
+                             int n_v_pad, int ns, const unsigned long long* tmax, const double* dgp, int8_t* out,
+                             int* rexp, double* diag, hipStream_t st);
+hipError_t launch_density_i8(const DensityDigitArgs& a, int ns, hipStream_t st);
 // D = sum of the split slices (+ diag on the diagonal if non-null), both triangles
 hipError_t launch_density_reduce(const double* Dpart, int nsplit, int n_v, const double* diag, double* D,
                                  hipStream_t st);

@@ -107,6 +107,77 @@ __global__ __launch_bounds__(256) void split_t_bf16_kernel(const double* T, int 
   }
 }
 
+// ---------------------------------------------------------------- INT8 digits
+// The same four matrices as balanced base-256 digits for the INT8 density kernel
+// (density_i8.hip): per row, Z = rint(v 2^(6 + 8 (NS-1) - E)) with 2^E above the
+// row's largest magnitude (tmax), digits d_t in [-128, 127] (|d_0| <= 64), row
+// value 2^(E - 6) sum_t d_t 2^(-8t).  Layout, chunk-major as for B (split.hip):
+// [q][m][n_v_pad/32][n_v_pad][NS][32] bytes, and the row exponents E - 6 in
+// rexp[q][m][n_v_pad] (0 for zero rows).  Thread (row r, quarter k4) holds 16
+// consecutive columns, i.e. one half of a 32-wide chunk: one 16-byte store per digit.
+template <int NS>
+__global__ __launch_bounds__(256) void split_t_i8_kernel(const double* T, int n_v, int n_v_pad, int nt,
+                                                         const unsigned long long* tmax, int8_t* out, int* rexp) {
+  __shared__ double tm[TB][LD];  // T[C-block row][A-block col]
+  const int A = blockIdx.x / nt, C = blockIdx.x - (blockIdx.x / nt) * nt, q = blockIdx.y;
+  const double* Tp = T + (size_t)q * n_v * n_v;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < TB * TB; e += 256) {
+    const int r = e >> 6, c = e & 63;
+    const int hr = C * TB + r, hc = A * TB + c;
+    tm[r][c] = (hr < n_v && hc < n_v) ? Tp[(size_t)hr * n_v + hc] : 0.0;
+  }
+  const int r = tid >> 2, k4 = tid & 3;
+  const int row = A * TB + r;
+  double x[16];
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    const int gc = C * TB + k4 * 16 + j;
+    x[j] = (row < n_v && gc < n_v) ? Tp[(size_t)row * n_v + gc] : 0.0;
+  }
+  __syncthreads();
+  double y[16];
+#pragma unroll
+  for (int j = 0; j < 16; ++j) y[j] = tm[k4 * 16 + j][r];
+
+  const int nck = n_v_pad >> 5;
+  const int ch = C * 2 + (k4 >> 1), kk0 = (k4 & 1) * 16;
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    const double mx = __longlong_as_double((long long)tmax[((size_t)q * 4 + m) * n_v_pad + row]);
+    int E = 0;
+    if (mx > 0.0) frexp(mx, &E);
+    if (C == 0 && k4 == 0) rexp[((size_t)q * 4 + m) * n_v_pad + row] = mx > 0.0 ? E - 6 : 0;
+    uint32_t word[NS][4];
+#pragma unroll
+    for (int t = 0; t < NS; ++t)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) word[t][u] = 0u;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      const double v = m == 0 ? x[j] : m == 1 ? y[j] : m == 2 ? 2.0 * x[j] - y[j] : 2.0 * y[j] - x[j];
+      long long Z = (mx > 0.0) ? (long long)rint(ldexp(v, 6 + 8 * (NS - 1) - E)) : 0;
+#pragma unroll
+      for (int t = NS - 1; t >= 1; --t) {
+        const long long d = ((Z + 128) & 255) - 128;
+        Z = (Z - d) >> 8;
+        word[t][j >> 2] |= ((uint32_t)d & 0xffu) << (8 * (j & 3));
+      }
+      word[0][j >> 2] |= ((uint32_t)Z & 0xffu) << (8 * (j & 3));
+    }
+    int8_t* dst = out + ((((size_t)q * 4 + m) * nck + ch) * n_v_pad + row) * (size_t)(32 * NS) + kk0;
+#pragma unroll
+    for (int t = 0; t < NS; ++t) {
+      u4 v4;
+      v4[0] = word[t][0];
+      v4[1] = word[t][1];
+      v4[2] = word[t][2];
+      v4[3] = word[t][3];
+      *reinterpret_cast<u4*>(dst + 32 * t) = v4;
+    }
+  }
+}
+
 // diag[a] += sum over pairs q and column blocks of w_q dgp[q][blk][a], in a fixed
 // order (strided per thread, then a fixed tree), so the result is reproducible
 __global__ __launch_bounds__(256) void diag_accumulate_kernel(const double* dgp, const int2* pairs, const double* pw,
@@ -143,6 +214,27 @@ hipError_t launch_split_t_bf16(const double* T, const int2* pairs, const double*
     case 2: hipLaunchKernelGGL(split_t_bf16_kernel<2>, grid, block, 0, st, T, n_v, n_v_pad, nt, tmax, out); break;
     case 3: hipLaunchKernelGGL(split_t_bf16_kernel<3>, grid, block, 0, st, T, n_v, n_v_pad, nt, tmax, out); break;
     case 4: hipLaunchKernelGGL(split_t_bf16_kernel<4>, grid, block, 0, st, T, n_v, n_v_pad, nt, tmax, out); break;
+    default: return hipErrorInvalidValue;
+  }
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(diag_accumulate_kernel, dim3(n_v), dim3(256), 0, st, dgp, pairs, pw, w, n_pairs, nt, n_v_pad,
+                     diag);
+  return hipGetLastError();
+}
+
+hipError_t launch_split_t_i8(const double* T, const int2* pairs, const double* pw, double w, int n_pairs, int n_v,
+                             int n_v_pad, int ns, const unsigned long long* tmax, const double* dgp, int8_t* out,
+                             int* rexp, double* diag, hipStream_t st) {
+  if (n_pairs <= 0) return hipSuccess;
+  if (n_v_pad % TB != 0 || n_v_pad < n_v) return hipErrorInvalidValue;
+  const int nt = n_v_pad / TB;
+  hipError_t e;
+  dim3 grid(nt * nt, n_pairs), block(256);
+  switch (ns) {
+    case 2: hipLaunchKernelGGL(split_t_i8_kernel<2>, grid, block, 0, st, T, n_v, n_v_pad, nt, tmax, out, rexp); break;
+    case 3: hipLaunchKernelGGL(split_t_i8_kernel<3>, grid, block, 0, st, T, n_v, n_v_pad, nt, tmax, out, rexp); break;
+    case 4: hipLaunchKernelGGL(split_t_i8_kernel<4>, grid, block, 0, st, T, n_v, n_v_pad, nt, tmax, out, rexp); break;
+    case 5: hipLaunchKernelGGL(split_t_i8_kernel<5>, grid, block, 0, st, T, n_v, n_v_pad, nt, tmax, out, rexp); break;
     default: return hipErrorInvalidValue;
   }
   if ((e = hipGetLastError()) != hipSuccess) return e;

@@ -64,7 +64,7 @@ def test_workspace_sizes(lib):
                                  dict(pair_batch=-5), dict(slices_gemm2=3), dict(precision=1, slices_gemm2=5),
                                  dict(precision=1, slices_gemm1=5), dict(precision=2, slices_gemm2=2),
                                  dict(precision=3, slices_gemm1=2), dict(precision=3, slices_gemm1=6),
-                                 dict(precision=3, slices_gemm2=5), dict(precision=3, n_aux=26209)])
+                                 dict(precision=3, slices_gemm2=6), dict(precision=3, n_aux=26209)])
 def test_invalid_options_rejected(lib, bad):
     kw = dict(n_core=10, n_act=0, n_vir=60, n_aux=200, s=0.5)
     kw.update({k: v for k, v in bad.items() if k in kw})
