@@ -1,6 +1,6 @@
 """GPU parity of the INT8-digit path (balanced base-256 digits per row, exact INT32
-level sums on the INT8 MFMA, BF16 density slices) against the FP64 oracle, through
-the C ABI.
+level sums on the INT8 MFMA, for V = B B^T and for the density product) against the
+FP64 oracle, through the C ABI.
 
 Bar derived from the arithmetic: with k digits every row is represented to within
 2^-(7 + 8(k-1)) of its largest element, the level sums are exact, and the levels
