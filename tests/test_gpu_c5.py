@@ -1,0 +1,58 @@
+"""The largest one-GPU workload at full size (c5: 120 core and 12 active holes,
+2000 virtuals, 6000 auxiliary functions, trace-12 Gamma_act) against the FP64
+oracle's expected values (tests/golden/c5_s0.5.json, written by make_golden.py
+from the oracle alone): energy, every occupation number, the kept count at
+p_o = 0.985 and the correction, for the FP64 path (1e-8 Eh) and the INT8-digit
+mixed path (1e-6 Eh).  The correction E_full - E_kept depends on the natural
+orbitals, which two FP64 eigensolvers (the library's and LAPACK in the oracle) give
+only to rounding: at |E_kept| ~ 7e7 Eh that alone moves E_kept by ~1e-16 |E_kept|
+per orbital rotation, so the FP64 bound on the correction is max(1e-8, 2e-15
+|E_kept|) Eh (1.3e-7 Eh here).  About a minute on the GPU machine, most of it drawing
+the 12.7 GB of inputs."""
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from gpu_common import dd_diff, need_gpu
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def test_c5_full_size_against_golden():
+    dp = need_gpu()
+    with open(os.path.join(HERE, "golden", "c5_s0.5.json")) as f:
+        gold = json.load(f)
+    tr = gold["truncation"][0]
+    occ_ref = np.array(gold["occ"])
+    print("c5: drawing inputs", flush=True)
+    inp = synth.config_inputs("c5")
+    d = dp.upload_inputs(inp)
+    del inp
+    for precision, tol, occ_tol in ((dp.FP64, 1e-8, 1e-11), (dp.INT8_SLICED, 1e-6, 1e-8)):
+        print(f"c5: precision {precision}", flush=True)
+        opts = dp.make_opts(120, 12, 2000, 6000, 0.5, precision=precision)
+        r = dp.build_vv_density(opts, d["eps_hole"], d["eps_vir"], d["gamma_act"], d["B"])
+        e = r["e_pt2"].cpu().numpy()
+        dE = dd_diff((float(e[0]), float(e[1])), gold["energy"])
+        t = dp.fno_truncate(r["D_vv"], tr["p_o"])
+        occ = t["occ"].cpu().numpy()
+        c = dp.pt2_energy_correction(opts, d["eps_hole"], d["eps_vir"], d["gamma_act"], d["B"], t["no_vecs"],
+                                     t["n_kept"], r["e_pt2"])
+        cc = c["correction"].cpu().numpy()
+        dC = dd_diff((float(cc[0]), float(cc[1])), tr["correction"])
+        print(f"  dE {dE:.3e} Eh, kept {t['n_kept']} (oracle {tr['n_kept']}), dcorr {dC:.3e} Eh, "
+              f"max dON {np.abs(occ - occ_ref).max():.3e}", flush=True)
+        e_kept = abs(sum(gold["energy"]) - sum(tr["correction"]))
+        ctol = max(tol, 2e-15 * e_kept)
+        assert dE <= tol
+        assert t["n_kept"] == tr["n_kept"]
+        assert dC <= ctol
+        assert np.abs(occ - occ_ref).max() <= occ_tol * occ_ref.max()
+        del r, t, c
+        torch.cuda.empty_cache()
