@@ -128,6 +128,47 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def active_particle_bench(args, wl, cfg):
+    """dfpt2_add_active_particle_density on the workload's sizes (needs n_act > 0)."""
+    import torch
+    import synth
+    import paper_2312_07008_amd as dp
+
+    s = args.s if args.s is not None else cfg["s"][0]
+    n_core, n_act, n_v, n_aux = cfg["sizes"]
+    if n_act == 0:
+        raise SystemExit("--active-particles needs a workload with active orbitals (c2, c5)")
+    inp = synth.generate(n_core, n_act, n_v, n_aux, 0, label=args.workload, active_particles=True, **wl["gen"])
+    d = dp.upload_inputs(inp)
+    del inp
+    opts = dp.make_opts(n_core, n_act, n_v, n_aux, s)
+    stream = torch.cuda.current_stream()
+    D = torch.zeros((n_v, n_v), dtype=torch.float64, device="cuda")
+    for _ in range(args.warmup):
+        dp.add_active_particle_density(opts, d["eps_hole"], d["eps_vir"], d["gamma_act"], d["B"], d["B_act"], D)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(args.steps):
+        dp.add_active_particle_density(opts, d["eps_hole"], d["eps_vir"], d["gamma_act"], d["B"], d["B_act"], D)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    n_h = n_core + n_act
+    K = n_h * n_h * n_act
+    flops = 2.0 * n_v * K * n_aux + 2.0 * n_v * K * n_act + 2.0 * n_v * n_v * K
+    res = {"metric": "Eq. A9 active-particle terms ms", "value": ms, "unit": "ms", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "higher_is_better": False, "dtype": "f64",
+           "data": "synthetic", "config": {"workload": f"{args.workload} sizes with active-particle integrals",
+                                           "n_core": n_core, "n_act": n_act, "n_vir": n_v, "n_aux": n_aux},
+           "gemm_flops": flops, "tflops": flops / (ms * 1e-3) / 1e12,
+           "roofline": {"bound": "mfma", "achieved": flops / (ms * 1e-3) / 1e12, "peak": PEAK_TFLOPS["f64"],
+                        "unit": "TFLOP/s", "frac": flops / (ms * 1e-3) / 1e12 / PEAK_TFLOPS["f64"],
+                        "traffic": None, "kernel": "gemm_f64 (amplitudes, eta, rank update) + mixing kernels"}}
+    log(f"active-particle terms: {ms:.2f} ms, {res['tflops']:.1f} TFLOP/s")
+    print(json.dumps(res), flush=True)
+
+
 def ladder_bench(args, wl, cfg):
     """Particle-particle ladder R^p = sum_cd (ac|bd) T^p_cd at N_V and at N_V' (kept NOs of the
     workload's FP64 pass at p_o): the (N_V/N_V')^4 saving the truncation is for (Sec. 2, Eq. 6)."""
@@ -216,6 +257,9 @@ def main():
                     help="instead of the pass: time the particle-particle ladder (the N_V^4 contraction of the "
                          "high-level step) in the full virtual space and in the space of the kept NOs of the "
                          "workload's FP64 pass, and print one JSON line for it")
+    ap.add_argument("--active-particles", action="store_true",
+                    help="instead of the pass: time dfpt2_add_active_particle_density (the Eq. A9 terms with an "
+                         "active particle index) on the workload's sizes, and print one JSON line for it")
     ap.add_argument("--ladder-amps", type=int, default=0,
                     help="amplitude matrices of the ladder run (default: every ordered core pair)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -237,6 +281,8 @@ def main():
     cfg = synth.CONFIGS[wl["base"]]
     if args.ladder:
         return ladder_bench(args, wl, cfg)
+    if args.active_particles:
+        return active_particle_bench(args, wl, cfg)
     s = args.s if args.s is not None else cfg["s"][0]
     p_o = args.p_o if args.p_o is not None else cfg["p_o"][0]
     prec = {"fp64": dp.FP64, "bf16": dp.BF16_SLICED, "fp8": dp.FP8_SLICED, "int8": dp.INT8_SLICED}[args.precision]
