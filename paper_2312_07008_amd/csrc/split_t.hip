@@ -41,42 +41,38 @@ typedef uint32_t u4 __attribute__((ext_vector_type(4)));
 
 // ---------------------------------------------------------------- slices
 // Workgroup = (row block A, column block C, pair q): rows A x columns C of the
-// four matrices.  Both tiles, T[A, C] (x = T[a][c]) and its mirror T[C, A]
-// (y = T[c][a]), are read into LDS with lane-contiguous loads; each thread then
-// holds one row and a 16-column quarter of x and y.  Each matrix's slices go
-// through an LDS staging area (the x tile's space, once x is in registers) laid
-// out like the output rows (64 rows x 512 bytes for 4 slices, one 16-byte pad
-// per row against bank conflicts), then out with lane-contiguous stores.
+// four matrices.  x = T[a][c] comes straight from global memory (thread = row,
+// 16-column quarter: 128 contiguous bytes), y = T[c][a] from the mirror tile
+// T[C, A] staged in LDS.  Each matrix's slices go through an LDS staging area
+// laid out like the output rows (64 rows x 512 bytes for 4 slices, one 16-byte
+// pad per row against bank conflicts), then out with lane-contiguous stores.
 template <int NS>
 __global__ __launch_bounds__(256) void split_t_bf16_kernel(const double* T, int n_v, int n_v_pad, int nt,
                                                            const unsigned long long* tmax, __bf16* out) {
   constexpr int RU4 = 4 * NS * 2;  // u4 per output row segment (64 columns)
   constexpr int SLD = RU4 + 1;     // padded staging row
-  constexpr int XLD = 66;          // padded tile row (doubles): also holds the staging area
-  static_assert(TB * SLD * 16 <= TB * XLD * 8, "staging fits in the x tile");
   __shared__ double tm[TB][LD];    // T[C-block row][A-block col]
-  __shared__ __attribute__((aligned(16))) double tx[TB * XLD];  // T[A rows][C cols], then the staging
-  u4* stage = reinterpret_cast<u4*>(tx);
+  __shared__ u4 stage[TB * SLD];
   const int A = blockIdx.x / nt, C = blockIdx.x - (blockIdx.x / nt) * nt, q = blockIdx.y;
   const double* Tp = T + (size_t)q * n_v * n_v;
   const int tid = threadIdx.x;
-  for (int e = tid; e < TB * TB; e += 256) {  // both tiles with lane-contiguous reads
+  for (int e = tid; e < TB * TB; e += 256) {
     const int r = e >> 6, c = e & 63;
     const int hr = C * TB + r, hc = A * TB + c;
     tm[r][c] = (hr < n_v && hc < n_v) ? Tp[(size_t)hr * n_v + hc] : 0.0;
-    const int xr = A * TB + r, xc = C * TB + c;
-    tx[r * XLD + c] = (xr < n_v && xc < n_v) ? Tp[(size_t)xr * n_v + xc] : 0.0;
   }
   const int r = tid >> 2, k4 = tid & 3;
   const int row = A * TB + r;
-  __syncthreads();
-  double x[16], y[16];
+  double x[16];
 #pragma unroll
   for (int j = 0; j < 16; ++j) {
-    x[j] = tx[r * XLD + k4 * 16 + j];
-    y[j] = tm[k4 * 16 + j][r];
+    const int gc = C * TB + k4 * 16 + j;
+    x[j] = (row < n_v && gc < n_v) ? Tp[(size_t)row * n_v + gc] : 0.0;
   }
-  __syncthreads();  // tx becomes the staging area
+  __syncthreads();
+  double y[16];
+#pragma unroll
+  for (int j = 0; j < 16; ++j) y[j] = tm[k4 * 16 + j][r];
 
   const size_t row_elems = (size_t)n_v_pad * NS;
 #pragma unroll
@@ -122,28 +118,27 @@ __global__ __launch_bounds__(256) void split_t_bf16_kernel(const double* T, int 
 template <int NS>
 __global__ __launch_bounds__(256) void split_t_i8_kernel(const double* T, int n_v, int n_v_pad, int nt,
                                                          const unsigned long long* tmax, int8_t* out, int* rexp) {
-  constexpr int XLD = 66;
-  __shared__ double tm[TB][LD];    // T[C-block row][A-block col]
-  __shared__ double tx[TB * XLD];  // T[A-block row][C-block col]
+  __shared__ double tm[TB][LD];  // T[C-block row][A-block col]
   const int A = blockIdx.x / nt, C = blockIdx.x - (blockIdx.x / nt) * nt, q = blockIdx.y;
   const double* Tp = T + (size_t)q * n_v * n_v;
   const int tid = threadIdx.x;
-  for (int e = tid; e < TB * TB; e += 256) {  // both tiles with lane-contiguous reads
+  for (int e = tid; e < TB * TB; e += 256) {
     const int r = e >> 6, c = e & 63;
     const int hr = C * TB + r, hc = A * TB + c;
     tm[r][c] = (hr < n_v && hc < n_v) ? Tp[(size_t)hr * n_v + hc] : 0.0;
-    const int xr = A * TB + r, xc = C * TB + c;
-    tx[r * XLD + c] = (xr < n_v && xc < n_v) ? Tp[(size_t)xr * n_v + xc] : 0.0;
   }
   const int r = tid >> 2, k4 = tid & 3;
   const int row = A * TB + r;
-  __syncthreads();
-  double x[16], y[16];
+  double x[16];
 #pragma unroll
   for (int j = 0; j < 16; ++j) {
-    x[j] = tx[r * XLD + k4 * 16 + j];
-    y[j] = tm[k4 * 16 + j][r];
+    const int gc = C * TB + k4 * 16 + j;
+    x[j] = (row < n_v && gc < n_v) ? Tp[(size_t)row * n_v + gc] : 0.0;
   }
+  __syncthreads();
+  double y[16];
+#pragma unroll
+  for (int j = 0; j < 16; ++j) y[j] = tm[k4 * 16 + j][r];
 
   const int nck = n_v_pad >> 5;
   const int ch = C * 2 + (k4 >> 1), kk0 = (k4 & 1) * 16;
