@@ -389,7 +389,8 @@ def main():
     F = nominal_flops(n_h, n_v, n_aux)
     value = F / (ms_pass * 1e-3) / 1e9
 
-    # dominant kernel: the pair kernel (V = B_i B_j^T + fused epilogue); issued MFMA flops:
+    # dominant kernel: the pair product V = B_i B_j^T (BF16: its own kernel, the epilogue
+    # runs after it; FP8, INT8, FP64: one kernel with the fused epilogue); issued MFMA flops:
     # 2 n_v^2 n_aux per computed unordered core pair and per operand-slice product
     ns1 = {"fp64": 1, "int8": 5}.get(args.precision, 4)
     products = ns1 * (ns1 + 1) // 2
@@ -401,16 +402,21 @@ def main():
     achieved = (products * 2.0 * n_v * n_v * n_aux * computed * args.steps) / (pk_ms * 1e-3) / 1e12 if pk_launch else None
     peak = PEAK_TFLOPS[dtype]
     kname = {"int8": "i8"}.get(args.precision, args.precision)
+    split_epi = prof["pair_epilogue"][1] > 0
+    if split_epi:
+        kid, kdesc = f"pair_v_bf16_kernel<{ns1},2>", "pair_v_bf16 (V = B_i B_j^T, 128 x 64 tiles"
+    else:
+        kid = f"pair_gemm_{kname}_kernel<{ns1},true>"
+        kdesc = f"pair_gemm_{kname if ns1 > 1 else 'f64'} (V = B_i B_j^T with the fused DSRG epilogue"
     roofline = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TOP/s" if dtype == "i8" else "TFLOP/s",
                 "frac": (achieved / peak) if achieved else None,
-                "traffic": recorded_traffic(f"pair_gemm_{kname}_kernel<{ns1},true>", args.workload)
-                if (ns1 > 1 and not screen_drops) else None,
-                "kernel": f"pair_gemm_{kname if ns1 > 1 else 'f64'} (V = B_i B_j^T, {products} slice products, "
-                          "fused DSRG epilogue)",
+                "traffic": recorded_traffic(kid, args.workload) if (ns1 > 1 and not screen_drops) else None,
+                "kernel": f"{kdesc}, {products} slice products)",
                 "traffic_unit": "HBM-side bytes per launch: FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 (factors from a "
                                 "1 GiB device copy), from the committed counter summary under profiles/",
                 "kernel_ms_per_launch": pk_ms / pk_launch if pk_launch else None,
                 "launches_per_pass": pk_launch // args.steps if pk_launch else 0,
+                "epilogue_ms_per_launch": (prof["pair_epilogue"][0] / prof["pair_epilogue"][1]) if split_epi else None,
                 "flops_per_unit": f"{products} x 2 n_v^2 n_aux per computed unordered core pair"}
 
     E = e.cpu().numpy()

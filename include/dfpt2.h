@@ -331,7 +331,8 @@ int pairscreen_build_mask(const float* pred, const double* log_scale, int64_t n_
  *   launches  host out [DFPT2_NSTAGE], number of timed launches per stage
  */
 enum {
-  DFPT2_STAGE_PAIR = 0,       /* pair kernel: V = B_i B_j^T + regularizer/energy epilogue */
+  DFPT2_STAGE_PAIR = 0,       /* pair product V = B_i B_j^T (with the fused regularizer/energy
+                                 epilogue where the product and the epilogue share a kernel) */
   DFPT2_STAGE_DENSITY = 1,    /* density kernel (D_vv accumulation) */
   DFPT2_STAGE_SPLIT = 2,      /* operand splitting into BF16/FP8 slices */
   DFPT2_STAGE_REDUCE = 3,     /* pair lists, reductions, finalization */
@@ -343,7 +344,8 @@ enum {
   DFPT2_STAGE_SPLIT_T = 9,    /* amplitude splitting into BF16 slices for the density */
   DFPT2_STAGE_LADDER_TRANSFORM = 10, /* particle-particle ladder: inputs to the kept NO basis */
   DFPT2_STAGE_LADDER = 11,    /* particle-particle ladder: integral and contraction GEMMs */
-  DFPT2_NSTAGE = 12
+  DFPT2_STAGE_PAIR_EPILOGUE = 12, /* regularizer/energy epilogue run as a kernel of its own */
+  DFPT2_NSTAGE = 13
 };
 int dfpt2_profile_enable(int on);
 int dfpt2_profile_read(double* ms, int64_t* launches);

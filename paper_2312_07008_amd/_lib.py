@@ -90,7 +90,7 @@ SIGNATURES = {
 }
 
 STAGES = ["pair", "density", "split", "reduce", "active", "eigh", "transform", "kept_pair", "screen", "split_t",
-          "ladder_transform", "ladder"]
+          "ladder_transform", "ladder", "pair_epilogue"]
 
 _lib = None
 

@@ -32,6 +32,7 @@ SOURCES = [
     "active_particle.hip",
     "split.hip",
     "pair_bf16.hip",
+    "pair_bf16_v.hip",
     "pair_fp8.hip",
     "pair_i8.hip",
     "split_t.hip",

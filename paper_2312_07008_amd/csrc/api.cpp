@@ -86,7 +86,8 @@ int plan_pass(const dfpt2_opts* o, PassPlan* pl, bool energy_only) {
   p.precision = o->precision;
   p.ns1 = o->slices_gemm1 ? o->slices_gemm1 : default_slices_gemm1(o->precision);
   p.n_v_pad_d = (p.n_v + 63) / 64 * 64;
-  p.n_v_pad = p.n_v_pad_d;  // slab rows of the sliced operands
+  // slab rows of the sliced operands: 128-multiple for BF16 (the 128 x 128-tile V kernel)
+  p.n_v_pad = p.precision == DFPT2_BF16_SLICED ? (p.n_v + 127) / 128 * 128 : p.n_v_pad_d;
   p.nTP1 = p.nTP;
   p.n_aux_pad = p.precision == DFPT2_FP8_SLICED ? (p.n_aux + 63) / 64 * 64 : (p.n_aux + 31) / 32 * 32;
   if ((p.precision == DFPT2_BF16_SLICED || p.precision == DFPT2_FP8_SLICED) && (p.ns1 < 2 || p.ns1 > 4))
@@ -250,7 +251,8 @@ int default_slices_gemm1(int precision) {
   return precision == DFPT2_FP64 ? 1 : precision == DFPT2_INT8_SLICED ? 5 : 4;
 }
 
-hipError_t launch_pair(const PairLaunch& L, const PairKernelArgs& a, int n_pairs, hipStream_t st) {
+hipError_t launch_pair(const PairLaunch& L, const PairKernelArgs& a, int n_pairs, hipStream_t st,
+                       ProfScope* product) {
   if (L.precision == DFPT2_FP64) return launch_pair_gemm_f64(a, n_pairs, st);
   PairSlicedArgs b{};
   b.Bs = L.Bs;
@@ -276,6 +278,13 @@ hipError_t launch_pair(const PairLaunch& L, const PairKernelArgs& a, int n_pairs
   b.e_weight = a.e_weight;
   if (L.precision == DFPT2_FP8_SLICED) return launch_pair_gemm_fp8(b, L.ns, n_pairs, st);
   if (L.precision == DFPT2_INT8_SLICED) return launch_pair_gemm_i8(b, L.ns, n_pairs, st);
+  if (b.T && b.n_v_pad % 128 == 0) {  // amplitudes stored: product and epilogue as two kernels
+    const hipError_t e = launch_pair_v_bf16(b, L.ns, n_pairs, st);
+    if (e != hipSuccess) return e;
+    if (product) product->close();
+    ProfScope ps(DFPT2_STAGE_PAIR_EPILOGUE, st);
+    return launch_pair_epi_bf16(b, n_pairs, st);
+  }
   return launch_pair_gemm_bf16(b, L.ns, n_pairs, st);
 }
 
@@ -505,7 +514,7 @@ int run_pass(const PassPlan& pl, const dfpt2_opts& o, const double* eps_h, const
     }
     {
       ProfScope ps(stage_pair, s);
-      if ((e = launch_pair(L, pa, np, s)) != hipSuccess) return hip_fail(e, "pair kernel");
+      if ((e = launch_pair(L, pa, np, s, &ps)) != hipSuccess) return hip_fail(e, "pair kernel");
     }
     {
       ProfScope ps(DFPT2_STAGE_REDUCE, s);

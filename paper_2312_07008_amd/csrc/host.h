@@ -61,7 +61,12 @@ struct PairLaunch {
   int n_v_pad, n_aux_pad;
   const double* norm2;
 };
-hipError_t launch_pair(const PairLaunch& L, const PairKernelArgs& a, int n_pairs, hipStream_t st);
+class ProfScope;
+// `product` (may be null): the caller's timer of the pair product; where the
+// epilogue runs as a kernel of its own, it is closed after the product and the
+// epilogue is timed as DFPT2_STAGE_PAIR_EPILOGUE
+hipError_t launch_pair(const PairLaunch& L, const PairKernelArgs& a, int n_pairs, hipStream_t st,
+                       ProfScope* product = nullptr);
 int default_slices_gemm1(int precision);
 
 // Stage timer scope (see dfpt2_profile_enable); no-op unless profiling is on.

@@ -1,0 +1,232 @@
+// Split-BF16 pair product in two kernels, for passes that store the amplitudes:
+//
+//   pair_v_bf16_kernel    V^{ij} = B_i B_j^T over 128 x 64 tiles of the full
+//                         n_v x n_v matrix, written in FP64 into the amplitude
+//                         buffer T[p] (same slices, levels and exact FP32 level
+//                         sums as pair_bf16.hip);
+//   pair_epi_bf16_kernel  per 64 x 64 tile pair (I <= J), V[I,J] and V[J,I]^T
+//                         read back into the MFMA register layout, then the
+//                         fused DSRG regularizer / energy / density-row epilogue
+//                         of pair_epilogue.h (paper App. A, Eq. A7), which
+//                         overwrites V with T in place.
+//
+// The fused kernel (pair_bf16.hip) computes V^{ij}[I,J] and V^{ji}[I,J] in one
+// workgroup so that the exchange partner of every element is lane-local; that
+// fixes its tile at 64 x 64 per product.  Its time is set by the bytes the
+// direct loads request (L2 hits and misses), so here the product runs on its own
+// with a 128 x 64 tile, a quarter fewer bytes per flop, at the cost of one FP64
+// write and two FP64 reads of V per element (a few ms per batch).  Measured
+// on the 80-core, 1200-virtual, 4000-auxiliary workload: 58.6 ms per batch of
+// 512 pairs for both kernels against 62.6 ms fused; 128 x 128 tiles (8 waves,
+// one workgroup per CU) 59.9 ms, 128 x 32 tiles (2 waves) 80.1 ms.
+//
+// Tile of the V kernel: 4 waves, wave (wr, wc) owns rows 64 wr .. 64 wr + 63
+// (two 32 x 32 MFMA blocks) and columns 32 wc .. 32 wc + 31; two workgroups per
+// CU.  Staging as in pair_bf16.hip: 16-wide contraction chunks of a 128-row and
+// a 64-row panel go from global memory straight into LDS (XOR-swizzled 128-byte
+// rows), double buffered; every wave moves 6 of the 24 kilobytes of a chunk.
+// The slabs must have a multiple of 128 rows.
+#include "common.h"
+#include "kernels.h"
+#include "pair_epilogue.h"
+
+namespace dfpt2 {
+
+namespace {
+constexpr int TV = 128;               // V tile edge
+constexpr int KC = 16;
+constexpr int SLOTS = 8;
+constexpr int kVWaveCols = 2;         // column waves: 128 x 64 tiles, 4 waves, two workgroups per CU
+constexpr int FLUSH_CHUNKS = 128 / KC;
+typedef uint32_t u4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) void lds_void;
+typedef __attribute__((address_space(1))) void gbl_void;
+
+__device__ inline int swz_v(int r) { return (r ^ (r >> 3)) & 7; }
+
+__device__ inline int xcd_block_v(int h, int nblk) {
+  const int x = h & 7, k = h >> 3, q = nblk >> 3, rem = nblk & 7;
+  return (x < rem) ? x * (q + 1) + k : rem * (q + 1) + (x - rem) * q + k;
+}
+}  // namespace
+
+// WC column waves: tile 128 x (32 WC) of V, 2 WC waves, wave (wr, wc) owns rows
+// 64 wr .. + 63 and columns 32 wc .. + 31
+template <int NS, int WC>
+__global__ __launch_bounds__(128 * WC, 4 / WC) void pair_v_bf16_kernel(PairSlicedArgs a, int nti, int ntj) {
+  static_assert(2 * NS <= SLOTS, "slices per LDS row");
+  constexpr int TJ = 32 * WC;                     // V tile columns
+  constexpr int KB_A = TV / 8, KB_B = TJ / 8;     // kilobytes of the two panels per chunk
+  constexpr int KB_W = (KB_A + KB_B) / (2 * WC);  // kilobytes per wave per chunk
+  static_assert(KB_W * 2 * WC == KB_A + KB_B, "whole kilobytes per wave");
+  __shared__ u4 lds0[(KB_A + KB_B) * 64];
+  __shared__ u4 lds1[(KB_A + KB_B) * 64];
+  const int per_pair = nti * ntj;
+  const int L = xcd_block_v(blockIdx.x, per_pair * a.n_blk_pairs);
+  const int p = L / per_pair, t = L - p * per_pair;
+  const int I = t / ntj, J = t - (t / ntj) * ntj;
+  const int2 pr = a.pairs[p];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int wr = w / WC, wc = w - (w / WC) * WC;
+
+  // kilobyte kb < KB_A of a chunk is rows 8 kb .. + 7 of panel A (B_i rows of tile I),
+  // kilobyte KB_A + kb rows 8 kb .. + 7 of panel B (B_j rows of tile J); wave w moves
+  // kilobytes KB_W w .. + KB_W - 1; lane l fills physical slot l % 8 of row l / 8
+  const int q_w = __builtin_amdgcn_readfirstlane(w);
+  const int row_bytes = a.n_aux_pad * NS * 2;
+  const char* panelA = static_cast<const char*>(a.Bs) + ((size_t)pr.x * a.n_v_pad + (size_t)I * TV) * row_bytes;
+  const char* panelB = static_cast<const char*>(a.Bs) + ((size_t)pr.y * a.n_v_pad + (size_t)J * TJ) * row_bytes;
+  const int l3 = lane >> 3, l7 = lane & 7;
+  auto src_off = [&](int kb) -> uint32_t {  // kb within its panel
+    const int row = 8 * kb + l3;
+    const int sl = l7 ^ swz_v(row);
+    const int ts = sl >> 1, h = sl & 1;
+    return (uint32_t)(row * row_bytes + (ts < NS ? ts * 32 + h * 16 : 0));
+  };
+  auto load_chunk = [&](int chunk, u4* buf) {
+    const size_t coff = (size_t)chunk * (KC * NS * 2);
+#pragma unroll
+    for (int m = 0; m < KB_W; ++m) {
+      const int kb = KB_W * q_w + m;  // wave-uniform
+      const char* src = kb < KB_A ? panelA + coff + src_off(kb) : panelB + coff + src_off(kb - KB_A);
+      __builtin_amdgcn_global_load_lds((gbl_void*)src, (lds_void*)(buf + kb * 64), 16, 0, 0);
+    }
+  };
+
+  f16v acc[2][3];
+  double dV[2][16];
+#pragma unroll
+  for (int b = 0; b < 2; ++b) {
+#pragma unroll
+    for (int l = 0; l < 3; ++l)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[b][l][r] = 0.f;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) dV[b][r] = 0.0;
+  }
+
+  const int nchunk = a.n_aux_pad / KC;
+  const int r32 = lane & 31, hq = lane >> 5;
+  const int rowB = wc * 32 + r32, fB = swz_v(rowB);
+  constexpr int PB = KB_A * 64;  // u4 offset of panel B in a buffer
+
+  auto compute = [&](const u4* buf, int c) {
+    bf8v fb[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s)
+      fb[s] = __builtin_bit_cast(bf8v, buf[PB + rowB * SLOTS + ((2 * s + hq) ^ fB)]);
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      const int rowA = wr * 64 + b * 32 + r32, fA = swz_v(rowA);
+      bf8v fa[NS];
+#pragma unroll
+      for (int s = 0; s < NS; ++s)
+        fa[s] = __builtin_bit_cast(bf8v, buf[rowA * SLOTS + ((2 * s + hq) ^ fA)]);
+#pragma unroll
+      for (int s = 0; s < NS; ++s)
+#pragma unroll
+        for (int u = 0; u + s < NS; ++u) {
+          const int lv = (s + u) < 2 ? (s + u) : 2;
+          acc[b][lv] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[s], fb[u], acc[b][lv], 0, 0, 0);
+        }
+    }
+    if ((c + 1) % FLUSH_CHUNKS == 0 || c + 1 == nchunk) {
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          dV[b][r] += (double)acc[b][0][r] + (double)acc[b][1][r];
+          acc[b][0][r] = 0.f;
+          acc[b][1][r] = 0.f;
+        }
+    }
+  };
+  auto step = [&](int c, u4* cur, u4* nxt) {
+    if (c + 1 < nchunk) load_chunk(c + 1, nxt);
+    compute(cur, c);
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+  };
+
+  load_chunk(0, lds0);
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  __syncthreads();
+  int c = 0;
+  for (; c + 1 < nchunk; c += 2) {
+    step(c, lds0, lds1);
+    step(c + 1, lds1, lds0);
+  }
+  if (c < nchunk) step(c, lds0, lds1);
+
+  // V^{ij}[ga][gb] in FP64 (register r of lane l: row 8(r/4) + 4(l/32) + r%4, column l%32)
+  const int n_v = a.n_v;
+  double* Vp = a.T + (size_t)p * n_v * n_v;
+  const int gb = J * TJ + wc * 32 + r32;
+  if (gb < n_v) {
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int ga = I * TV + wr * 64 + b * 32 + 8 * (r >> 2) + 4 * hq + (r & 3);
+        if (ga < n_v) Vp[(size_t)ga * n_v + gb] = dV[b][r] + (double)acc[b][2][r];
+      }
+  }
+}
+
+// Epilogue pass over 64 x 64 tile pairs (I <= J) of the V written above.
+__global__ __launch_bounds__(256) void pair_epi_bf16_kernel(PairSlicedArgs a) {
+  __shared__ double scratch[272];
+  const int L = xcd_block_v(blockIdx.x, a.nTP * a.n_blk_pairs);
+  const int p = L / a.nTP, tp = L - p * a.nTP;
+  int I, J;
+  tile_pair(tp, a.nt, I, J);
+  const int2 pr = a.pairs[p];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int wr = w >> 1, wc = w & 1, r32 = lane & 31, hq = lane >> 5;
+  const int n_v = a.n_v;
+  const double* Vp = a.T + (size_t)p * n_v * n_v;
+  const int gb = J * 64 + wc * 32 + r32;
+  double dP[16], dQ[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int ga = I * 64 + wr * 32 + 8 * (r >> 2) + 4 * hq + (r & 3);
+    const bool ok = ga < n_v && gb < n_v;
+    dP[r] = ok ? Vp[(size_t)ga * n_v + gb] : 0.0;  // V^{ij}_{ab}
+    dQ[r] = ok ? Vp[(size_t)gb * n_v + ga] : 0.0;  // V^{ji}_{ab} = V^{ij}_{ba}
+  }
+  if (pr.x == pr.y) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) dQ[r] = dP[r];
+  }
+  __syncthreads();  // every read of this tile pair's V precedes the T written over it
+  sliced_pair_epilogue<true>(a, p, tp, I, J, pr.x, pr.y, dP, dQ, scratch);
+}
+
+hipError_t launch_pair_v_bf16(const PairSlicedArgs& a, int ns, int n_pairs, hipStream_t st) {
+  if (n_pairs <= 0) return hipSuccess;
+  if (!a.T || a.n_v_pad % TV != 0) return hipErrorInvalidValue;
+  constexpr int WC = kVWaveCols;
+  const int nti = (a.n_v + TV - 1) / TV, ntj = (a.n_v + 32 * WC - 1) / (32 * WC);
+  if ((long long)nti * ntj * n_pairs > 0x7fffffffLL) return hipErrorInvalidValue;
+  PairSlicedArgs b = a;
+  b.n_blk_pairs = n_pairs;
+  dim3 gv(nti * ntj * n_pairs), bv(128 * WC);
+  switch (ns) {
+    case 2: hipLaunchKernelGGL((pair_v_bf16_kernel<2, WC>), gv, bv, 0, st, b, nti, ntj); break;
+    case 3: hipLaunchKernelGGL((pair_v_bf16_kernel<3, WC>), gv, bv, 0, st, b, nti, ntj); break;
+    case 4: hipLaunchKernelGGL((pair_v_bf16_kernel<4, WC>), gv, bv, 0, st, b, nti, ntj); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_pair_epi_bf16(const PairSlicedArgs& a, int n_pairs, hipStream_t st) {
+  if (n_pairs <= 0) return hipSuccess;
+  if (!a.T || (long long)a.nTP * n_pairs > 0x7fffffffLL) return hipErrorInvalidValue;
+  PairSlicedArgs b = a;
+  b.n_blk_pairs = n_pairs;
+  hipLaunchKernelGGL(pair_epi_bf16_kernel, dim3(a.nTP * n_pairs), dim3(256), 0, st, b);
+  return hipGetLastError();
+}
+
+}  // namespace dfpt2

@@ -34,6 +34,15 @@ def test_exports_every_declared_symbol(lib):
         assert n in _lib.SIGNATURES, n
 
 
+def test_stage_names_match_header():
+    """The Python stage list follows the header's DFPT2_STAGE_* values, in order."""
+    src = open(os.path.join(ROOT, "include", "dfpt2.h")).read()
+    vals = {m.group(1).lower(): int(m.group(2)) for m in re.finditer(r"DFPT2_STAGE_(\w+)\s*=\s*(\d+)", src)}
+    nstage = int(re.search(r"DFPT2_NSTAGE\s*=\s*(\d+)", src).group(1))
+    assert sorted(vals.values()) == list(range(nstage))
+    assert [name for name, _ in sorted(vals.items(), key=lambda kv: kv[1])] == _lib.STAGES
+
+
 def test_version_and_status_strings(lib):
     assert b"gfx950" in lib.dfpt2_version()
     assert lib.dfpt2_status_string(0) == b"ok"
