@@ -86,8 +86,11 @@ int plan_pass(const dfpt2_opts* o, PassPlan* pl, bool energy_only) {
   p.precision = o->precision;
   p.ns1 = o->slices_gemm1 ? o->slices_gemm1 : default_slices_gemm1(o->precision);
   p.n_v_pad_d = (p.n_v + 63) / 64 * 64;
-  // slab rows of the sliced operands: 128-multiple for BF16 (the 128 x 128-tile V kernel)
+  // slab rows of the sliced operands and rows of the density operands: 128-multiples
+  // for BF16 (the 128-row tiles of the V kernel and of the density kernel)
   p.n_v_pad = p.precision == DFPT2_BF16_SLICED ? (p.n_v + 127) / 128 * 128 : p.n_v_pad_d;
+  p.n_v_rows_t = p.precision == DFPT2_BF16_SLICED ? (p.n_v + 127) / 128 * 128 : p.n_v_pad_d;
+  p.nTD = density_bf16_tiles(p.nt);
   p.nTP1 = p.nTP;
   p.n_aux_pad = p.precision == DFPT2_FP8_SLICED ? (p.n_aux + 63) / 64 * 64 : (p.n_aux + 31) / 32 * 32;
   if ((p.precision == DFPT2_BF16_SLICED || p.precision == DFPT2_FP8_SLICED) && (p.ns1 < 2 || p.ns1 > 4))
@@ -107,14 +110,15 @@ int plan_pass(const dfpt2_opts* o, PassPlan* pl, bool energy_only) {
   if (p.precision == DFPT2_INT8_SLICED && p.ns2 >= 2 && (long long)(p.ns2 - 1) * 16384 * p.n_v_pad_d >= 0x7fffffffLL)
     return fail(DFPT2_ERR_INVALID_ARG, "n_vir too large for exact INT8 density sums with %d digits", p.ns2);
   if (energy_only) p.ns2 = 1;
-  // split-BF16 density: splits of the pair range chosen so that tile pairs x splits
+  // sliced density: splits of the pair range chosen so that workgroup tiles x splits
   // fill whole rounds of two workgroups per CU on 256 CUs
   p.nsplit2 = 1;
   if (p.ns2 >= 2) {
     double best = 1e30;
     const int cap = p.batch < 64 ? p.batch : 64;
+    const int tiles = p.precision == DFPT2_BF16_SLICED ? p.nTD : p.nTP;
     for (int k = 1; k <= cap; ++k) {
-      const double w = (double)p.nTP * k;
+      const double w = (double)tiles * k;
       const double rounds = std::ceil(w / 512.0);
       const double waste = (rounds * 512.0 - w) / w + (w < 2048.0 ? 1.0 : 0.0);
       if (waste < best - 1e-12) {
@@ -149,7 +153,7 @@ int plan_pass(const dfpt2_opts* o, PassPlan* pl, bool energy_only) {
   p.off_rexp = take(p.precision == DFPT2_INT8_SLICED ? sizeof(int) * (size_t)p.n_h * p.n_v_pad : 0);
   // density operands: BF16 slices, or INT8 digits (+ row exponents) with INT8 precision
   const size_t t_bytes = p.precision == DFPT2_INT8_SLICED ? 1 : sizeof(__bf16);
-  p.off_Ts = take(p.ns2 >= 2 ? t_bytes * 4 * (size_t)p.batch * p.n_v_pad_d * p.n_v_pad_d * p.ns2 : 0);
+  p.off_Ts = take(p.ns2 >= 2 ? t_bytes * 4 * (size_t)p.batch * p.n_v_rows_t * p.n_v_pad_d * p.ns2 : 0);
   p.off_Texp = take(p.ns2 >= 2 && p.precision == DFPT2_INT8_SLICED ? sizeof(int) * 4 * (size_t)p.batch * p.n_v_pad_d
                                                                     : 0);
   p.off_dg = take(p.ns2 >= 2 ? sizeof(double) * (size_t)p.batch * (p.n_v_pad_d / 64) * p.n_v_pad_d : 0);
@@ -553,8 +557,9 @@ int run_pass(const PassPlan& pl, const dfpt2_opts& o, const double* eps_h, const
       __bf16* Ts = reinterpret_cast<__bf16*>(ws + pl.off_Ts);
       {
         ProfScope ps(DFPT2_STAGE_SPLIT_T, s);
-        if ((e = launch_split_t_bf16(T, pairs + p0, nullptr, pl.w_density, np, pl.n_v, pl.n_v_pad_d, pl.ns2, pa.tmax,
-                                     pa.dgp, Ts, reinterpret_cast<double*>(ws + pl.off_diag), s)) != hipSuccess)
+        if ((e = launch_split_t_bf16(T, pairs + p0, nullptr, pl.w_density, np, pl.n_v, pl.n_v_pad_d, pl.n_v_rows_t,
+                                     pl.ns2, pa.tmax, pa.dgp, Ts, reinterpret_cast<double*>(ws + pl.off_diag), s)) !=
+            hipSuccess)
           return hip_fail(e, "amplitude split");
       }
       DensitySlicedArgs ds{};
@@ -565,7 +570,8 @@ int run_pass(const PassPlan& pl, const dfpt2_opts& o, const double* eps_h, const
       ds.n_v = pl.n_v;
       ds.n_v_pad = pl.n_v_pad_d;
       ds.nt = pl.nt;
-      ds.nTP = pl.nTP;
+      ds.nTP = pl.nTD;
+      ds.rows_pad = pl.n_v_rows_t;
       ds.n_pairs = np;
       ds.nsplit = pl.nsplit2 < np ? pl.nsplit2 : np;
       ds.w = pl.w_density;

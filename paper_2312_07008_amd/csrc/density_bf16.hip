@@ -4,23 +4,34 @@
 //
 // Per unordered pair the contribution is X1 Y1^T + X2 Y2^T (split_t.hip gives
 // the slices of the rows of X1 = T, X2 = T^T, Y1 = 2T - T^T, Y2 = 2T^T - T).
-// As in the pair kernel, the slice products of level s + t - 1 <= NS are kept;
-// within one pair every product of a row a of X and a row b of Y is an integer
-// multiple of one unit, so the level-1 and level-2 sums are exact in FP32 over
-// 128 contraction steps and are added into FP64 every 128 steps and at the end
-// of every pair (with the pair's weight); levels >= 3 are summed in FP32 per pair.
-// D is symmetric: only tiles (A <= B) are formed.  Diagonal elements are left
-// out: split_t.hip sums them exactly in FP64 (the rows of X and Y there carry the
+// As in the pair kernel, the slice products of level s + t - 1 <= NS are kept.
+// Within one product of one pair every product of a row a of X and a row b of Y
+// is an integer multiple of one unit (the two rows' scales), so the level-1 and
+// level-2 sums are exact in FP32 over 128 contraction steps; they are added into
+// FP64 every 128 steps and at the end of each of the pair's two products (with
+// the pair's weight), and levels >= 3 are summed in FP32 per product.  The two
+// products carry different units, so the contraction runs over X1 / Y1 first
+// and X2 / Y2 after it, with one set of accumulators.  D is symmetric: only
+// tiles on or above the diagonal are formed.  Diagonal elements are left out:
+// split_t.hip sums them exactly in FP64 (the rows of X and Y there carry the
 // same amplitudes, so the dropped slice products would not average out).
 //
-// Workgroup = (tile pair (A, B), split s): split s owns a contiguous range of
-// pairs and accumulates into its own slice Dpart[s]; the slices are summed in a
-// fixed order afterwards (density_reduce_kernel), so results are bitwise
-// reproducible.  Staging as in pair_bf16.hip: four 64-row panels per 16-wide
-// chunk (X1[A], Y1[B], X2[A], Y2[B]) go from global memory straight into LDS,
-// double buffered, in XOR-swizzled 128-byte rows; every wave owns one 32 x 32
-// block of the tile and sums both products into it.  The 1-D launch is
-// remapped so that every XCD walks a contiguous range of (split, tile pair):
+// Workgroup = (128 x 64 tile (I, J) of D with J >= 2I in 64-wide units, split s):
+// split s owns a contiguous range of pairs and accumulates into its own slice
+// Dpart[s]; the slices are summed in a fixed order afterwards
+// (density_reduce_kernel), so results are bitwise reproducible.  A 128 x 64
+// tile moves 192 rows per contraction chunk for 8192 outputs (a 64 x 64 tile
+// pair of both products at once: 256 rows for 8192), 25% fewer bytes per flop.
+// Four waves, wave (wr, wc) owns rows 64 wr .. + 63 (two 32 x 32 MFMA blocks)
+// and columns 32 wc .. + 31; on a diagonal tile (J = 2I) rows 64 .. 127 lie
+// below the diagonal and their two waves only help with the loads.  Rows of X
+// beyond n_v_pad (the last row tile when n_v_pad / 64 is odd) are loaded only
+// there: the operand matrices are rows_pad rows apart, and those rows are never
+// written or used.  Staging as in pair_bf16_v.hip: 16-wide chunks of the 128-row
+// X panel and the 64-row Y panel go from global memory straight into LDS
+// (XOR-swizzled 128-byte rows), double buffered, 24 KB per buffer, two
+// workgroups per CU.  The 1-D launch is
+// remapped so that every XCD walks a contiguous range of (split, tile):
 // workgroups resident on one XCD read the same pairs' slices.
 #include "common.h"
 #include "kernels.h"
@@ -28,10 +39,13 @@
 namespace dfpt2 {
 
 namespace {
-constexpr int TM = 64;
+constexpr int TX = 128;  // rows of D per tile (X panel)
+constexpr int TY = 64;   // columns of D per tile (Y panel)
 constexpr int KC = 16;
 constexpr int SLOTS = 8;
-constexpr int PANEL_U4 = TM * SLOTS;
+constexpr int KB_X = TX / 8, KB_Y = TY / 8;  // kilobytes of the two panels per chunk
+constexpr int KB_W = (KB_X + KB_Y) / 4;      // kilobytes per wave per chunk
+constexpr int PY = KB_X * 64;                // u4 offset of the Y panel in a buffer
 constexpr int FLUSH_CHUNKS = 128 / KC;
 typedef uint32_t u4 __attribute__((ext_vector_type(4)));
 typedef __attribute__((address_space(3))) void lds_void;
@@ -43,110 +57,123 @@ __device__ inline int xcd_block_d(int h, int nblk) {
   const int x = h & 7, k = h >> 3, q = nblk >> 3, rem = nblk & 7;
   return (x < rem) ? x * (q + 1) + k : rem * (q + 1) + (x - rem) * q + k;
 }
+
+// tile td of the row-major list of (I, J), J = 2I .. nt - 1
+__device__ inline void density_tile(int td, int nt, int& I, int& J) {
+  int i = 0, rem = td;
+  while (rem >= nt - 2 * i) {
+    rem -= nt - 2 * i;
+    ++i;
+  }
+  I = i;
+  J = 2 * i + rem;
+}
 }  // namespace
 
 template <int NS>
 __global__ __launch_bounds__(256, 2) void density_bf16_kernel(DensitySlicedArgs a) {
   static_assert(2 * NS <= SLOTS, "slices per LDS row");
-  __shared__ u4 lds0[4 * PANEL_U4];
-  __shared__ u4 lds1[4 * PANEL_U4];
+  static_assert(KB_W * 4 == KB_X + KB_Y, "whole kilobytes per wave");
+  __shared__ u4 lds0[(KB_X + KB_Y) * 64];
+  __shared__ u4 lds1[(KB_X + KB_Y) * 64];
   const int L = xcd_block_d(blockIdx.x, a.nTP * a.nsplit);
-  const int split = L / a.nTP, tp = L - split * a.nTP;
-  int A, Bt;
-  tile_pair(tp, a.nt, A, Bt);
+  const int split = L / a.nTP, td = L - split * a.nTP;
+  int I, J;
+  density_tile(td, a.nt, I, J);
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int wr = w >> 1, wc = w & 1;
+  const bool below = (J == 2 * I) && wr == 1;  // wave-uniform
   const int n_v = a.n_v;
   const int p0 = (int)((long long)split * a.n_pairs / a.nsplit);  // balanced pair ranges
   const int p1 = (int)((long long)(split + 1) * a.n_pairs / a.nsplit);
-  const int ncc = a.n_v_pad / KC;
-  const int total = (p1 > p0) ? (p1 - p0) * ncc : 0;
+  const int ncc = a.n_v_pad / KC;  // chunks per product
+  const int per_pair = 2 * ncc;
+  const int total = (p1 > p0) ? (p1 - p0) * per_pair : 0;
 
-  // direct loads: wave w fills panel w (X1 rows A, Y1 rows B, X2 rows A, Y2 rows B)
+  // kilobyte kb < KB_X of a chunk is rows 8 kb .. + 7 of the X panel (rows of
+  // tile I), kilobyte KB_X + kb rows 8 kb .. + 7 of the Y panel (rows of tile J);
+  // wave w moves kilobytes KB_W w .. + KB_W - 1; lane l fills physical slot l % 8
+  // of row l / 8
   const int q_w = __builtin_amdgcn_readfirstlane(w);
-  const int mat_w = (q_w == 0) ? 0 : (q_w == 1) ? 2 : (q_w == 2) ? 1 : 3;
-  const int tile_w = (q_w == 0 || q_w == 2) ? A : Bt;
   const int row_bytes = a.n_v_pad * NS * 2;
-  const size_t pair_bytes = (size_t)4 * a.n_v_pad * row_bytes;
-  const char* panel0 = reinterpret_cast<const char*>(a.Ts) + ((size_t)mat_w * a.n_v_pad + tile_w * TM) * row_bytes;
+  const size_t mat_bytes = (size_t)a.rows_pad * row_bytes;
+  const char* Ts = reinterpret_cast<const char*>(a.Ts);
   const int l3 = lane >> 3, l7 = lane & 7;
-  auto src_off = [&](int m) -> uint32_t {
-    const int sl = l7 ^ l3 ^ m;
+  auto src_off = [&](int kb) -> uint32_t {  // kb within its panel
+    const int row = 8 * kb + l3;
+    const int sl = l7 ^ swz8(row);
     const int t = sl >> 1, h = sl & 1;
-    return (uint32_t)((8 * m + l3) * row_bytes + (t < NS ? t * 32 + h * 16 : 0));
+    return (uint32_t)(row * row_bytes + (t < NS ? t * 32 + h * 16 : 0));
   };
+  // step idx: pair p0 + idx / per_pair, product h (0: X1 Y1^T, 1: X2 Y2^T), chunk ch
   auto load_chunk = [&](int idx, u4* buf) {
-    const int p = p0 + idx / ncc, ch = idx - (idx / ncc) * ncc;
-    const char* base = panel0 + (size_t)p * pair_bytes + (size_t)ch * (KC * NS * 2);
+    const int pi = idx / per_pair, rem = idx - pi * per_pair;
+    const int h = rem >= ncc ? 1 : 0, ch = rem - h * ncc;
+    const char* pb = Ts + (size_t)(p0 + pi) * 4 * mat_bytes + (size_t)ch * (KC * NS * 2);
+    const char* pX = pb + (size_t)h * mat_bytes + (size_t)I * TX * row_bytes;
+    const char* pY = pb + (size_t)(2 + h) * mat_bytes + (size_t)J * TY * row_bytes;
 #pragma unroll
-    for (int m = 0; m < 8; ++m)
-      __builtin_amdgcn_global_load_lds((gbl_void*)(base + src_off(m)), (lds_void*)(buf + q_w * PANEL_U4 + m * 64),
-                                       16, 0, 0);
+    for (int m = 0; m < KB_W; ++m) {
+      const int kb = KB_W * q_w + m;  // wave-uniform
+      const char* src = kb < KB_X ? pX + src_off(kb) : pY + src_off(kb - KB_X);
+      __builtin_amdgcn_global_load_lds((gbl_void*)src, (lds_void*)(buf + kb * 64), 16, 0, 0);
+    }
   };
 
-  f16v accP[3], accQ[3];
-  double dD[16];
+  f16v acc[2][3];
+  double dD[2][16];
 #pragma unroll
-  for (int l = 0; l < 3; ++l)
+  for (int b = 0; b < 2; ++b) {
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      accP[l][r] = 0.f;
-      accQ[l][r] = 0.f;
-    }
+    for (int l = 0; l < 3; ++l)
 #pragma unroll
-  for (int r = 0; r < 16; ++r) dD[r] = 0.0;
+      for (int r = 0; r < 16; ++r) acc[b][l][r] = 0.f;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) dD[b][r] = 0.0;
+  }
 
   const int r32 = lane & 31, hq = lane >> 5;
-  const int rowA = wr * 32 + r32, rowB = wc * 32 + r32;
-  const int fA = swz8(rowA), fB = swz8(rowB);
-
+  const int rowY = wc * 32 + r32, fY = swz8(rowY);
   auto compute = [&](const u4* buf) {
-    bf8v fa[NS], fb[NS];
+    if (below) return;
+    bf8v fb[NS];
 #pragma unroll
-    for (int t = 0; t < NS; ++t) {
-      fa[t] = __builtin_bit_cast(bf8v, buf[0 * PANEL_U4 + rowA * SLOTS + ((2 * t + hq) ^ fA)]);
-      fb[t] = __builtin_bit_cast(bf8v, buf[1 * PANEL_U4 + rowB * SLOTS + ((2 * t + hq) ^ fB)]);
+    for (int s = 0; s < NS; ++s) fb[s] = __builtin_bit_cast(bf8v, buf[PY + rowY * SLOTS + ((2 * s + hq) ^ fY)]);
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      const int rowX = wr * 64 + b * 32 + r32, fX = swz8(rowX);
+      bf8v fa[NS];
+#pragma unroll
+      for (int s = 0; s < NS; ++s) fa[s] = __builtin_bit_cast(bf8v, buf[rowX * SLOTS + ((2 * s + hq) ^ fX)]);
+#pragma unroll
+      for (int s = 0; s < NS; ++s)
+#pragma unroll
+        for (int u = 0; u + s < NS; ++u) {
+          const int lv = (s + u) < 2 ? (s + u) : 2;
+          acc[b][lv] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[s], fb[u], acc[b][lv], 0, 0, 0);
+        }
     }
-#pragma unroll
-    for (int s = 0; s < NS; ++s)
-#pragma unroll
-      for (int t = 0; t + s < NS; ++t) {
-        const int lv = (s + t) < 2 ? (s + t) : 2;
-        accP[lv] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[s], fb[t], accP[lv], 0, 0, 0);
-      }
-#pragma unroll
-    for (int t = 0; t < NS; ++t) {
-      fa[t] = __builtin_bit_cast(bf8v, buf[2 * PANEL_U4 + rowA * SLOTS + ((2 * t + hq) ^ fA)]);
-      fb[t] = __builtin_bit_cast(bf8v, buf[3 * PANEL_U4 + rowB * SLOTS + ((2 * t + hq) ^ fB)]);
-    }
-#pragma unroll
-    for (int s = 0; s < NS; ++s)
-#pragma unroll
-      for (int t = 0; t + s < NS; ++t) {
-        const int lv = (s + t) < 2 ? (s + t) : 2;
-        accQ[lv] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[s], fb[t], accQ[lv], 0, 0, 0);
-      }
   };
-  // flush after chunk ch of the current pair (weight wp)
-  auto flush = [&](int ch, double wp) {
-    const bool pair_end = (ch + 1 == ncc);
-    if ((ch + 1) % FLUSH_CHUNKS == 0 || pair_end) {
+  // after chunk ch of the current product (weight wp)
+  auto flush = [&](int ch, bool prod_end, double wp) {
+    if ((ch + 1) % FLUSH_CHUNKS == 0 || prod_end) {
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        dD[r] += wp * (((double)accP[0][r] + (double)accP[1][r]) + ((double)accQ[0][r] + (double)accQ[1][r]));
-        accP[0][r] = 0.f;
-        accP[1][r] = 0.f;
-        accQ[0][r] = 0.f;
-        accQ[1][r] = 0.f;
-      }
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          dD[b][r] += wp * ((double)acc[b][0][r] + (double)acc[b][1][r]);
+          acc[b][0][r] = 0.f;
+          acc[b][1][r] = 0.f;
+        }
     }
-    if (pair_end) {
+    if (prod_end) {
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        dD[r] += wp * ((double)accP[2][r] + (double)accQ[2][r]);
-        accP[2][r] = 0.f;
-        accQ[2][r] = 0.f;
-      }
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          dD[b][r] += wp * (double)acc[b][2][r];
+          acc[b][2][r] = 0.f;
+        }
     }
   };
   // pair weight: one ordered pair w, halved for i == j (both orders are the same)
@@ -156,16 +183,24 @@ __global__ __launch_bounds__(256, 2) void density_bf16_kernel(DensitySlicedArgs 
     if (a.pw) wp *= a.pw[p];
     return wp;
   };
-  int cp = p0, cch = 0;  // pair and chunk of the step being computed
+  int cp = p0, cch = 0, half = 0;  // pair, chunk and product of the step being computed
   double wp = (total > 0) ? weight(p0) : 0.0;
   auto step = [&](int idx, u4* cur, u4* nxt) {
     if (idx + 1 < total) load_chunk(idx + 1, nxt);
     compute(cur);
-    flush(cch, wp);
-    if (++cch == ncc) {
+    const bool prod_end = (cch + 1 == ncc);
+    flush(cch, prod_end, wp);
+    if (prod_end) {
       cch = 0;
-      ++cp;
-      if (cp < p1) wp = weight(cp);
+      if (half) {
+        half = 0;
+        ++cp;
+        if (cp < p1) wp = weight(cp);
+      } else {
+        half = 1;
+      }
+    } else {
+      ++cch;
     }
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();
@@ -183,23 +218,35 @@ __global__ __launch_bounds__(256, 2) void density_bf16_kernel(DensitySlicedArgs 
     if (idx < total) step(idx, lds0, lds1);
   }
 
-  // epilogue (32x32 layout: register r of lane l is row 8(r/4) + 4(l/32) + r%4, column l%32)
+  // D tile (32x32 layout: register r of lane l is row 8(r/4) + 4(l/32) + r%4, column l%32)
+  if (below) return;
   double* Dp = a.Dpart + (size_t)split * n_v * n_v;
-  const int gb = Bt * TM + wc * 32 + r32;
+  const int gb = J * TY + wc * 32 + r32;
   if (gb < n_v) {
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      const int ga = A * TM + wr * 32 + 8 * (r >> 2) + 4 * hq + (r & 3);
-      if (ga >= n_v || ga == gb) continue;  // the diagonal comes from the exact FP64 sum (split_t.hip)
-      double* dst = Dp + (size_t)ga * n_v + gb;
-      *dst = a.accumulate ? *dst + dD[r] : dD[r];
-    }
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int ga = I * TX + wr * 64 + b * 32 + 8 * (r >> 2) + 4 * hq + (r & 3);
+        if (ga >= n_v || ga == gb) continue;  // the diagonal comes from the exact FP64 sum (split_t.hip)
+        double* dst = Dp + (size_t)ga * n_v + gb;
+        *dst = a.accumulate ? *dst + dD[b][r] : dD[b][r];
+      }
   }
+}
+
+int density_bf16_tiles(int nt) {
+  int n = 0;
+  for (int i = 0; 2 * i < nt; ++i) n += nt - 2 * i;
+  return n;
 }
 
 hipError_t launch_density_bf16(const DensitySlicedArgs& a, int ns, hipStream_t st) {
   if (a.n_pairs <= 0) return hipSuccess;
-  if (a.n_v_pad % TM != 0 || (long long)a.nTP * a.nsplit > 0x7fffffffLL) return hipErrorInvalidValue;
+  // the X panels of the last row tile reach row 128 ceil(nt / 2) - 1
+  if (a.n_v_pad != 64 * a.nt || a.rows_pad % TX != 0 || a.rows_pad < TX * ((a.nt + 1) / 2) ||
+      a.nTP != density_bf16_tiles(a.nt) || (long long)a.nTP * a.nsplit > 0x7fffffffLL)
+    return hipErrorInvalidValue;
   dim3 grid(a.nTP * a.nsplit), block(256);
   switch (ns) {
     case 2: hipLaunchKernelGGL(density_bf16_kernel<2>, grid, block, 0, st, a); break;

@@ -32,6 +32,8 @@ struct PassPlan {
   int ns1;          // slices per operand of the pair product (mixed precision)
   int n_v_pad, n_aux_pad;  // slab rows and columns of the sliced operands
   int n_v_pad_d;           // 64-multiple of n_v: layout of the density slices and row data
+  int n_v_rows_t;          // rows per density operand matrix (128-multiple for the BF16 density kernel)
+  int nTD;                 // workgroup tiles of the split-BF16 density kernel
   size_t off_pairs, off_count, off_T, off_epart, off_tpart, off_pe, off_tn2, off_Dpart, off_Bs, off_scales, off_norm2, off_rexp, off_Ts, off_Texp, off_dg, off_tmax, off_diag;
   // active holes
   int n_ca, n_aa_un, cpb, act_cap;

@@ -79,21 +79,26 @@ hipError_t launch_density_f64(const DensityKernelArgs& a, hipStream_t st);
 
 // split-BF16 density: amplitude slices (split_t.hip) and the sliced product
 struct DensitySlicedArgs {
-  const __bf16* Ts;     // [n_pairs][4][n_v_pad][n_v_pad/16][ns][16] (split_t.hip)
+  const __bf16* Ts;     // [n_pairs][4][rows_pad][n_v_pad/16][ns][16] (split_t.hip)
   const double* pw;     // [n_pairs] per-pair weight, or null
   const int2* pairs;    // [n_pairs]
   double* Dpart;        // [nsplit][n_v][n_v]
-  int n_v, n_v_pad, nt, nTP, n_pairs, nsplit;
+  int n_v, n_v_pad, nt, nTP, n_pairs, nsplit;  // nTP = density_bf16_tiles(nt)
+  int rows_pad;         // rows per operand matrix: a multiple of 128, >= 128 ceil(nt / 2)
   double w;             // weight of one ordered pair
   int accumulate;
 };
+// workgroup tiles (128 x 64, on or above the diagonal) of the split-BF16 density kernel
+int density_bf16_tiles(int nt);
 // slices of the four density operands of every pair of a batch (T: [n_pairs][n_v][n_v]),
 // from the row maxima tmax ([n_pairs][4][n_v_pad]) the pair kernel recorded, plus
 // diag[a] += the exact FP64 diagonal of the batch's contribution from the pair
-// kernel's partial sums dgp ([n_pairs][n_v_pad/64][n_v_pad])
+// kernel's partial sums dgp ([n_pairs][n_v_pad/64][n_v_pad]); the operand matrices
+// are rows_pad rows apart (a multiple of 64, >= n_v_pad); rows n_v .. n_v_pad - 1
+// are written as zeros, rows n_v_pad .. rows_pad - 1 are not written
 hipError_t launch_split_t_bf16(const double* T, const int2* pairs, const double* pw, double w, int n_pairs, int n_v,
-                               int n_v_pad, int ns, const unsigned long long* tmax, const double* dgp, __bf16* out,
-                               double* diag, hipStream_t st);
+                               int n_v_pad, int rows_pad, int ns, const unsigned long long* tmax, const double* dgp,
+                               __bf16* out, double* diag, hipStream_t st);
 hipError_t launch_density_bf16(const DensitySlicedArgs& a, int ns, hipStream_t st);
 
 // INT8-digit density: digits of the four operands (split_t.hip) and the digit product

@@ -13,8 +13,11 @@
 // so the density kernel can sum the slice products of one pair exactly in FP32.
 // The digits are taken from that rounded integer with balanced base-512 digit
 // extraction, which gives the same represented value as slicing by successive
-// round-to-nearest steps.  Output per pair q: [q][m][n_v_pad][n_v_pad/16][ns][16]
-// (rows and columns >= n_v are zeros), the chunk-interleaved layout of B's slices.
+// round-to-nearest steps.  Output per pair q: [q][m][rows_pad][n_v_pad/16][ns][16]
+// (rows and columns n_v .. n_v_pad - 1 are zeros), the chunk-interleaved layout
+// of B's slices.  The matrix stride rows_pad >= n_v_pad lets the density kernel
+// load 128-row panels; rows n_v_pad .. rows_pad - 1 are not written (the density
+// kernel's waves that load them form no products from them).
 //
 // The diagonal of the pair's contribution, w_q sum_c (X1 Y1 + X2 Y2)[a][c] =
 // w_q sum_c 2 (x^2 - x y + y^2) with x = T[a][c], y = T[c][a], is summed here in
@@ -47,8 +50,8 @@ typedef uint32_t u4 __attribute__((ext_vector_type(4)));
 // laid out like the output rows (64 rows x 512 bytes for 4 slices, one 16-byte
 // pad per row against bank conflicts), then out with lane-contiguous stores.
 template <int NS>
-__global__ __launch_bounds__(256) void split_t_bf16_kernel(const double* T, int n_v, int n_v_pad, int nt,
-                                                           const unsigned long long* tmax, __bf16* out) {
+__global__ __launch_bounds__(256) void split_t_bf16_kernel(const double* T, int n_v, int n_v_pad, int rows_pad,
+                                                           int nt, const unsigned long long* tmax, __bf16* out) {
   constexpr int RU4 = 4 * NS * 2;  // u4 per output row segment (64 columns)
   constexpr int SLD = RU4 + 1;     // padded staging row
   __shared__ double tm[TB][LD];    // T[C-block row][A-block col]
@@ -98,7 +101,7 @@ __global__ __launch_bounds__(256) void split_t_bf16_kernel(const double* T, int 
       stage[r * SLD + k4 * (2 * NS) + 2 * t + 1] = __builtin_bit_cast(u4, sl[t][1]);
     }
     __syncthreads();
-    __bf16* dst = out + ((size_t)q * 4 + m) * n_v_pad * row_elems + (size_t)C * (4 * NS * 16);
+    __bf16* dst = out + ((size_t)q * 4 + m) * rows_pad * row_elems + (size_t)C * (4 * NS * 16);
     for (int f = tid; f < TB * RU4; f += 256) {
       const int rr = f / RU4, pc = f - rr * RU4;
       reinterpret_cast<u4*>(dst + (size_t)(A * TB + rr) * row_elems)[pc] = stage[rr * SLD + pc];
@@ -203,17 +206,17 @@ __global__ __launch_bounds__(256) void diag_accumulate_kernel(const double* dgp,
 }
 
 hipError_t launch_split_t_bf16(const double* T, const int2* pairs, const double* pw, double w, int n_pairs, int n_v,
-                               int n_v_pad, int ns, const unsigned long long* tmax, const double* dgp, __bf16* out,
-                               double* diag, hipStream_t st) {
+                               int n_v_pad, int rows_pad, int ns, const unsigned long long* tmax, const double* dgp,
+                               __bf16* out, double* diag, hipStream_t st) {
   if (n_pairs <= 0) return hipSuccess;
-  if (n_v_pad % TB != 0 || n_v_pad < n_v) return hipErrorInvalidValue;
+  if (n_v_pad % TB != 0 || n_v_pad < n_v || rows_pad % TB != 0 || rows_pad < n_v_pad) return hipErrorInvalidValue;
   const int nt = n_v_pad / TB;
   hipError_t e;
   dim3 grid(nt * nt, n_pairs), block(256);
   switch (ns) {
-    case 2: hipLaunchKernelGGL(split_t_bf16_kernel<2>, grid, block, 0, st, T, n_v, n_v_pad, nt, tmax, out); break;
-    case 3: hipLaunchKernelGGL(split_t_bf16_kernel<3>, grid, block, 0, st, T, n_v, n_v_pad, nt, tmax, out); break;
-    case 4: hipLaunchKernelGGL(split_t_bf16_kernel<4>, grid, block, 0, st, T, n_v, n_v_pad, nt, tmax, out); break;
+    case 2: hipLaunchKernelGGL(split_t_bf16_kernel<2>, grid, block, 0, st, T, n_v, n_v_pad, rows_pad, nt, tmax, out); break;
+    case 3: hipLaunchKernelGGL(split_t_bf16_kernel<3>, grid, block, 0, st, T, n_v, n_v_pad, rows_pad, nt, tmax, out); break;
+    case 4: hipLaunchKernelGGL(split_t_bf16_kernel<4>, grid, block, 0, st, T, n_v, n_v_pad, rows_pad, nt, tmax, out); break;
     default: return hipErrorInvalidValue;
   }
   if ((e = hipGetLastError()) != hipSuccess) return e;
