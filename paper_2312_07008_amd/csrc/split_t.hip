@@ -45,17 +45,15 @@ typedef uint32_t u4 __attribute__((ext_vector_type(4)));
 // ---------------------------------------------------------------- slices
 // Workgroup = (row block A, column block C, pair q): rows A x columns C of the
 // four matrices.  x = T[a][c] comes straight from global memory (thread = row,
-// 16-column quarter: 128 contiguous bytes), y = T[c][a] from the mirror tile
-// T[C, A] staged in LDS.  Each matrix's slices go through an LDS staging area
-// laid out like the output rows (64 rows x 512 bytes for 4 slices, one 16-byte
-// pad per row against bank conflicts), then out with lane-contiguous stores.
-template <int NS>
+// 16-column quarter: 128 contiguous bytes, 16-byte loads when n_v is even),
+// y = T[c][a] from the mirror tile T[C, A] staged in LDS.  The thread's 16
+// columns are exactly one 16-wide chunk of the output row, so its slices of each
+// matrix (32 NS contiguous bytes) are stored straight from registers; the four
+// threads of a row write 128 NS contiguous bytes.
+template <int NS, bool VEC>
 __global__ __launch_bounds__(256) void split_t_bf16_kernel(const double* T, int n_v, int n_v_pad, int rows_pad,
                                                            int nt, const unsigned long long* tmax, __bf16* out) {
-  constexpr int RU4 = 4 * NS * 2;  // u4 per output row segment (64 columns)
-  constexpr int SLD = RU4 + 1;     // padded staging row
-  __shared__ double tm[TB][LD];    // T[C-block row][A-block col]
-  __shared__ u4 stage[TB * SLD];
+  __shared__ double tm[TB][LD];  // T[C-block row][A-block col]
   const int A = blockIdx.x / nt, C = blockIdx.x - (blockIdx.x / nt) * nt, q = blockIdx.y;
   const double* Tp = T + (size_t)q * n_v * n_v;
   const int tid = threadIdx.x;
@@ -67,10 +65,21 @@ __global__ __launch_bounds__(256) void split_t_bf16_kernel(const double* T, int 
   const int r = tid >> 2, k4 = tid & 3;
   const int row = A * TB + r;
   double x[16];
+  if (VEC) {  // n_v even: rows start 16-byte aligned and columns come in pairs below n_v
+    const double2* src = reinterpret_cast<const double2*>(Tp + (size_t)row * n_v + C * TB + k4 * 16);
 #pragma unroll
-  for (int j = 0; j < 16; ++j) {
-    const int gc = C * TB + k4 * 16 + j;
-    x[j] = (row < n_v && gc < n_v) ? Tp[(size_t)row * n_v + gc] : 0.0;
+    for (int j = 0; j < 8; ++j) {
+      const int gc = C * TB + k4 * 16 + 2 * j;
+      const double2 v = (row < n_v && gc < n_v) ? src[j] : make_double2(0.0, 0.0);
+      x[2 * j] = v.x;
+      x[2 * j + 1] = v.y;
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      const int gc = C * TB + k4 * 16 + j;
+      x[j] = (row < n_v && gc < n_v) ? Tp[(size_t)row * n_v + gc] : 0.0;
+    }
   }
   __syncthreads();
   double y[16];
@@ -95,18 +104,14 @@ __global__ __launch_bounds__(256) void split_t_bf16_kernel(const double* T, int 
         sl[t][j >> 3][j & 7] = (__bf16)ldexpf((float)d, E - 8 - 9 * t);
       }
     }
+    // chunk C * 4 + k4 of row `row` of matrix m: [NS][16] bf16
+    u4* dst = reinterpret_cast<u4*>(out + ((size_t)q * 4 + m) * rows_pad * row_elems + (size_t)row * row_elems +
+                                    (size_t)(C * 4 + k4) * (NS * 16));
 #pragma unroll
     for (int t = 0; t < NS; ++t) {
-      stage[r * SLD + k4 * (2 * NS) + 2 * t] = __builtin_bit_cast(u4, sl[t][0]);
-      stage[r * SLD + k4 * (2 * NS) + 2 * t + 1] = __builtin_bit_cast(u4, sl[t][1]);
+      dst[2 * t] = __builtin_bit_cast(u4, sl[t][0]);
+      dst[2 * t + 1] = __builtin_bit_cast(u4, sl[t][1]);
     }
-    __syncthreads();
-    __bf16* dst = out + ((size_t)q * 4 + m) * rows_pad * row_elems + (size_t)C * (4 * NS * 16);
-    for (int f = tid; f < TB * RU4; f += 256) {
-      const int rr = f / RU4, pc = f - rr * RU4;
-      reinterpret_cast<u4*>(dst + (size_t)(A * TB + rr) * row_elems)[pc] = stage[rr * SLD + pc];
-    }
-    __syncthreads();
   }
 }
 
@@ -213,12 +218,23 @@ hipError_t launch_split_t_bf16(const double* T, const int2* pairs, const double*
   const int nt = n_v_pad / TB;
   hipError_t e;
   dim3 grid(nt * nt, n_pairs), block(256);
+  const bool vec = (n_v % 2) == 0;
+#define SPLIT_T_BF16(NS_)                                                                                          \
+  do {                                                                                                             \
+    if (vec)                                                                                                       \
+      hipLaunchKernelGGL((split_t_bf16_kernel<NS_, true>), grid, block, 0, st, T, n_v, n_v_pad, rows_pad, nt, tmax, \
+                         out);                                                                                     \
+    else                                                                                                           \
+      hipLaunchKernelGGL((split_t_bf16_kernel<NS_, false>), grid, block, 0, st, T, n_v, n_v_pad, rows_pad, nt,      \
+                         tmax, out);                                                                               \
+  } while (0)
   switch (ns) {
-    case 2: hipLaunchKernelGGL(split_t_bf16_kernel<2>, grid, block, 0, st, T, n_v, n_v_pad, rows_pad, nt, tmax, out); break;
-    case 3: hipLaunchKernelGGL(split_t_bf16_kernel<3>, grid, block, 0, st, T, n_v, n_v_pad, rows_pad, nt, tmax, out); break;
-    case 4: hipLaunchKernelGGL(split_t_bf16_kernel<4>, grid, block, 0, st, T, n_v, n_v_pad, rows_pad, nt, tmax, out); break;
+    case 2: SPLIT_T_BF16(2); break;
+    case 3: SPLIT_T_BF16(3); break;
+    case 4: SPLIT_T_BF16(4); break;
     default: return hipErrorInvalidValue;
   }
+#undef SPLIT_T_BF16
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(diag_accumulate_kernel, dim3(n_v), dim3(256), 0, st, dgp, pairs, pw, w, n_pairs, nt, n_v_pad,
                      diag);
