@@ -6,14 +6,17 @@
 //      every workgroup) and p = tau A v, then a kernel for the rank-2 update
 //      A -= v w^T + w v^T with w = p - (tau/2)(p.v) v.
 //   2. Splitting at negligible off-diagonal entries, then every eigenvalue by
-//      bisection on Sturm counts (one thread per eigenvalue).
+//      multisection on Sturm counts (one wave per eigenvalue, 64 points a round).
 //   3. Eigenvectors of the tridiagonal matrix by inverse iteration with a
 //      partially pivoted LU of T - lambda I; eigenvalues closer than a small
 //      multiple of ||T|| form a group that one thread handles in order,
 //      orthogonalizing every iterate against the group's earlier vectors.
 //   4. Back-transformation Z <- H_0 H_1 ... H_{n-3} Z, one workgroup per block
 //      of columns held in LDS, all reflectors applied in one launch.
-//   5. Columns sorted by eigenvalue and oriented so that the largest-magnitude
+//   5. One first-order orthonormalization of all columns (two FP64 GEMMs): it
+//      restores orthogonality between vectors of close eigenvalues that inverse
+//      iteration did not group.
+//   6. Columns sorted by eigenvalue and oriented so that the largest-magnitude
 //      component is positive.
 #include <cmath>
 #include <cfloat>
@@ -166,32 +169,51 @@ __device__ int sturm_count(const double* d, const double* e, int s, int t, doubl
   return cnt;
 }
 
-// Thread g: the (g - start)-th eigenvalue of the block containing position g.
-__global__ void tridiag_bisect(int n, const double* d, const double* e, const int* blk_start,
-                               const int* blk_end, const double* tnorm, double* lam) {
-  const int g = blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= n) return;
+// Wave g (four per workgroup): the (g - start)-th eigenvalue of the block
+// containing position g, by multisection: each lane takes the Sturm count at one
+// of 64 interior points of the bracket, and the bracket shrinks to the interval
+// between the highest point whose count is <= j and the lowest point above it
+// whose count is > j (65x per round instead of 2x, so ~9 rounds of parallel
+// counts instead of ~55 sequential ones).  The invariant count(lo) <= j <
+// count(hi) holds whatever the rounding of the points or counts; the stopping
+// rule is that of the bisection below.
+__global__ __launch_bounds__(256) void tridiag_multisect(int n, const double* d, const double* e,
+                                                         const int* blk_start, const int* blk_end,
+                                                         const double* tnorm, double* lam) {
+  const int g = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (g >= n) return;  // wave-uniform
   const int s = blk_start[g], t = blk_end[g], j = g - s;
   double lo = DBL_MAX, hi = -DBL_MAX;
-  for (int i = s; i < t; ++i) {
+  for (int i = s + lane; i < t; i += 64) {
     const double r = (i > s ? fabs(e[i - 1]) : 0.0) + (i + 1 < t ? fabs(e[i]) : 0.0);
     lo = fmin(lo, d[i] - r);
     hi = fmax(hi, d[i] + r);
+  }
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+    lo = fmin(lo, __shfl_xor(lo, o, 64));
+    hi = fmax(hi, __shfl_xor(hi, o, 64));
   }
   const double nrm = fmax(*tnorm, DBL_MIN);
   const double pivmin = DBL_MIN * fmax(1.0, nrm * nrm) * 4.0;
   const double pad = 2.0 * DBL_EPSILON * nrm * (t - s) + 2.0 * pivmin;
   lo -= pad;
   hi += pad;
-  // invariant: count(lo) <= j < count(hi)
-  for (int it = 0; it < 200; ++it) {
-    const double mid = 0.5 * (lo + hi);
-    if (mid <= lo || mid >= hi) break;
+  for (int it = 0; it < 64; ++it) {
     if (hi - lo <= 2.0 * DBL_EPSILON * fmax(fabs(lo), fabs(hi)) + pivmin) break;
-    if (sturm_count(d, e, s, t, mid, pivmin) > j) hi = mid;
-    else lo = mid;
+    const double x = fmin(fmax(lo + (double)(lane + 1) * ((hi - lo) / 65.0), lo), hi);
+    const bool le = (x <= lo) ? true : (x >= hi) ? false : (sturm_count(d, e, s, t, x, pivmin) <= j);
+    const unsigned long long m = __ballot(le);
+    const int klo = m ? 63 - __clzll((long long)m) : -1;
+    const unsigned long long above = ~m & (klo >= 63 ? 0ull : (~0ull << (klo + 1)));
+    const int khi = above ? __ffsll((long long)above) - 1 : 64;
+    const double nlo = klo >= 0 ? __shfl(x, klo, 64) : lo;
+    const double nhi = khi < 64 ? __shfl(x, khi, 64) : hi;
+    if (!(nlo > lo || nhi < hi)) break;  // the points no longer split the bracket
+    lo = nlo;
+    hi = nhi;
   }
-  lam[g] = 0.5 * (lo + hi);
+  if (lane == 0) lam[g] = 0.5 * (lo + hi);
 }
 
 // ------------------------------------------------------------ inverse iteration
@@ -248,25 +270,40 @@ __device__ void lu_factor(const double* d, const double* e, int s, int t, double
 }
 
 // Solve in place: x (column g of X over positions [s, t)) <- (T - lam I)^{-1} x.
-__device__ void lu_solve(int s, int t, const LuCols& L, int n, int g, double* X, int xcol) {
+// The values each step produces for the next are carried in registers, so the
+// loads of a step depend on nothing written by the one before.
+__device__ void lu_solve(int s, int t, const LuCols& L, int n, int g, double* __restrict__ X, int xcol) {
+  const double* __restrict__ u1 = L.u1;
+  const double* __restrict__ u2 = L.u2;
+  const double* __restrict__ u3 = L.u3;
+  const double* __restrict__ lm = L.l;
+  const double* __restrict__ pv = L.piv;
+  double yi = X[(size_t)s * n + xcol];
+#pragma unroll 4
   for (int i = s; i < t - 1; ++i) {
     const size_t o = (size_t)i * n + g;
-    double yi = X[(size_t)i * n + xcol], yn = X[(size_t)(i + 1) * n + xcol];
-    if (L.piv[o] != 0.0) {
+    double yn = X[(size_t)(i + 1) * n + xcol];
+    if (pv[o] != 0.0) {
       const double tmp = yi;
       yi = yn;
       yn = tmp;
     }
-    yn -= L.l[o] * yi;
+    yn -= lm[o] * yi;
     X[(size_t)i * n + xcol] = yi;
-    X[(size_t)(i + 1) * n + xcol] = yn;
+    yi = yn;
   }
+  X[(size_t)(t - 1) * n + xcol] = yi;
+  double x1 = 0.0, x2 = 0.0;  // the solved X[i + 1], X[i + 2]
+#pragma unroll 4
   for (int i = t - 1; i >= s; --i) {
     const size_t o = (size_t)i * n + g;
     double v = X[(size_t)i * n + xcol];
-    if (i + 1 < t) v -= L.u2[o] * X[(size_t)(i + 1) * n + xcol];
-    if (i + 2 < t) v -= L.u3[o] * X[(size_t)(i + 2) * n + xcol];
-    X[(size_t)i * n + xcol] = v / L.u1[o];
+    if (i + 1 < t) v -= u2[o] * x1;
+    if (i + 2 < t) v -= u3[o] * x2;
+    v = v / u1[o];
+    X[(size_t)i * n + xcol] = v;
+    x2 = x1;
+    x1 = v;
   }
 }
 
@@ -405,6 +442,17 @@ __global__ void eig_rank(int n, const double* lam, int* rank) {
 }
 
 // out column dst(g) = sign-oriented column g; descending: dst = n-1-rank
+// M = I - U with U = strictly upper part of E + diag(E) / 2, where E = Z^T Z - I
+// arrives as G = Z^T Z in M (in place)
+__global__ void orth_correction(int n, double* M) {
+  const size_t nn = (size_t)n * n;
+  for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < nn; k += (size_t)gridDim.x * blockDim.x) {
+    const int i = (int)(k / n), j = (int)(k - (size_t)i * n);
+    const double g = M[k];
+    M[k] = i < j ? -g : i == j ? 1.0 - 0.5 * (g - 1.0) : 0.0;
+  }
+}
+
 __global__ void eig_permute(int n, const double* lam, const int* rank, const double* Zin, double* w_out,
                             double* Z_out, int descending) {
   const int g = blockIdx.x;
@@ -523,7 +571,7 @@ int eigh_run(const double* A_in, int n, double* w_out, double* Z_out, char* ws, 
   hipLaunchKernelGGL(tridiag_tail, dim3(1), dim3(64), 0, st, A, n, d, e);
   // 2. split + bisection
   hipLaunchKernelGGL(tridiag_split, dim3(1), dim3(64), 0, st, n, d, e, blk_start, blk_end, tnorm);
-  hipLaunchKernelGGL(tridiag_bisect, dim3((n + 127) / 128), dim3(128), 0, st, n, d, e, blk_start, blk_end, tnorm,
+  hipLaunchKernelGGL(tridiag_multisect, dim3((n + 3) / 4), dim3(256), 0, st, n, d, e, blk_start, blk_end, tnorm,
                      lam);
   // 3. inverse iteration
   LuCols L{lu, lu + nn, lu + 2 * nn, lu + 3 * nn, lu + 4 * nn};
@@ -542,9 +590,23 @@ int eigh_run(const double* A_in, int n, double* w_out, double* Z_out, char* ws, 
     hipLaunchKernelGGL(tridiag_backtransform, dim3((n + cw - 1) / cw), dim3(256), (size_t)n * cw * 8, st, n, Vs,
                        tau, X, cw);
   }
-  // 5. sort + orient
+  // 5. one first-order orthonormalization of all columns: with G = Z^T Z = I + E
+  //    and E small, Z <- Z (I - U), U = strict upper part of E + diag(E) / 2, leaves
+  //    Z^T Z = I + O(E^2).  E is non-negligible only between vectors of close
+  //    eigenvalues whose gap inverse iteration left unresolved (relative gaps
+  //    just above the grouping tolerance), and mixing those moves the residuals
+  //    by no more than their gap times E.  The LU columns are free by now.
+  double* G = lu;
+  double* Zo = lu + nn;
+  if ((err = gemm_f64(X, n, 0, 1, X, n, 0, 0, G, n, 0, n, n, n, 1, 1.0, 0.0, st)) != hipSuccess)
+    return hip_fail(err, "eigh orthonormalization");
+  hipLaunchKernelGGL(orth_correction, dim3((unsigned)((nn + 255) / 256 < 65535 ? (nn + 255) / 256 : 65535)),
+                     dim3(256), 0, st, n, G);
+  if ((err = gemm_f64(X, n, 0, 0, G, n, 0, 0, Zo, n, 0, n, n, n, 1, 1.0, 0.0, st)) != hipSuccess)
+    return hip_fail(err, "eigh orthonormalization");
+  // 6. sort + orient
   hipLaunchKernelGGL(eig_rank, dim3((n + 255) / 256), dim3(256), 0, st, n, lam, rank);
-  hipLaunchKernelGGL(eig_permute, dim3(n), dim3(256), 0, st, n, lam, rank, X, w_out, Z_out, descending);
+  hipLaunchKernelGGL(eig_permute, dim3(n), dim3(256), 0, st, n, lam, rank, Zo, w_out, Z_out, descending);
   if ((err = hipGetLastError()) != hipSuccess) return hip_fail(err, "eigh launch");
   prof_all.close();
   int hs = 0;

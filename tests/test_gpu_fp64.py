@@ -90,7 +90,7 @@ def _gpu_eigh(A):
 @pytest.mark.parametrize("kind,n", [("random", 1), ("random", 2), ("random", 3), ("random", 97),
                                     ("random", 256), ("identity", 40), ("diag_repeat", 33),
                                     ("blocks", 60), ("psd_lowrank", 120), ("clustered", 80), ("zeros", 5),
-                                    ("zeros", 1)])
+                                    ("zeros", 1), ("random", 1200), ("graded", 300)])
 def test_eigh_against_lapack(kind, n):
     rng = np.random.default_rng(n)
     if kind == "random":
@@ -110,6 +110,11 @@ def test_eigh_against_lapack(kind, n):
     elif kind == "psd_lowrank":
         X = rng.standard_normal((n, 7))
         A = X @ X.T
+    elif kind == "graded":  # occupation-number-like spectrum over 15 decades
+        Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+        lam = 10.0 ** np.linspace(-12.0, 3.0, n)
+        A = (Q * lam) @ Q.T
+        A = 0.5 * (A + A.T)
     else:  # clustered: eigenvalues 1 +- 1e-12 * k
         Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
         lam = np.concatenate([1.0 + 1e-12 * np.arange(n // 2), 5.0 + rng.random(n - n // 2)])
