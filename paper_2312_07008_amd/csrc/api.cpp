@@ -282,7 +282,7 @@ hipError_t launch_pair(const PairLaunch& L, const PairKernelArgs& a, int n_pairs
   b.e_weight = a.e_weight;
   if (L.precision == DFPT2_FP8_SLICED) return launch_pair_gemm_fp8(b, L.ns, n_pairs, st);
   if (L.precision == DFPT2_INT8_SLICED) return launch_pair_gemm_i8(b, L.ns, n_pairs, st);
-  if (b.T && b.n_v_pad % 128 == 0) {  // amplitudes stored: product and epilogue as two kernels
+  if (b.T || b.Vr) {  // amplitudes stored: product and epilogue as two kernels
     const hipError_t e = launch_pair_v_bf16(b, L.ns, n_pairs, st);
     if (e != hipSuccess) return e;
     if (product) product->close();

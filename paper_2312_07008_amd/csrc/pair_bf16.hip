@@ -1,6 +1,8 @@
 // Split-BF16 pair kernel: V = B_i B_j^T from BF16 slices on the 32x32x16 BF16
 // MFMA, with the same fused DSRG regularizer/energy epilogue as the FP64
-// kernel (paper App. A, Eq. A7).
+// kernel (paper App. A, Eq. A7).  Launched for energy-only passes (the kept-space
+// energy); passes that store the amplitudes run the product over larger tiles and
+// the epilogue as a second kernel (pair_bf16_v.hip).
 //
 // Operands come from split.hip: each FP64 row of B is sum_t slice_t with
 // slice_t an 8-bit integer times 2^(E - 8 - 9(t-1)).  The product of two rows
@@ -201,22 +203,18 @@ __global__ __launch_bounds__(256, 2) void pair_gemm_bf16_kernel(PairSlicedArgs a
 hipError_t launch_pair_gemm_bf16(const PairSlicedArgs& a, int ns, int n_pairs, hipStream_t st) {
   if (n_pairs <= 0) return hipSuccess;
   if ((long long)a.nTP * n_pairs > 0x7fffffffLL) return hipErrorInvalidValue;
+  // energy only: passes that store amplitudes run the product and the epilogue
+  // as two kernels (pair_bf16_v.hip)
+  if (a.T || a.Vr) return hipErrorInvalidValue;
   PairSlicedArgs b = a;
   b.n_blk_pairs = n_pairs;
   dim3 grid(a.nTP * n_pairs), block(256);
-  const bool store = a.T != nullptr || a.Vr != nullptr;
-#define DFPT2_LAUNCH(NS_)                                                                          \
-  if (store)                                                                                       \
-    hipLaunchKernelGGL((pair_gemm_bf16_kernel<NS_, true>), grid, block, 0, st, b);                  \
-  else                                                                                             \
-    hipLaunchKernelGGL((pair_gemm_bf16_kernel<NS_, false>), grid, block, 0, st, b);
   switch (ns) {
-    case 2: DFPT2_LAUNCH(2) break;
-    case 3: DFPT2_LAUNCH(3) break;
-    case 4: DFPT2_LAUNCH(4) break;
+    case 2: hipLaunchKernelGGL((pair_gemm_bf16_kernel<2, false>), grid, block, 0, st, b); break;
+    case 3: hipLaunchKernelGGL((pair_gemm_bf16_kernel<3, false>), grid, block, 0, st, b); break;
+    case 4: hipLaunchKernelGGL((pair_gemm_bf16_kernel<4, false>), grid, block, 0, st, b); break;
     default: return hipErrorInvalidValue;
   }
-#undef DFPT2_LAUNCH
   return hipGetLastError();
 }
 
