@@ -11,8 +11,9 @@
 //      partially pivoted LU of T - lambda I; eigenvalues closer than a small
 //      multiple of ||T|| form a group that one thread handles in order,
 //      orthogonalizing every iterate against the group's earlier vectors.
-//   4. Back-transformation Z <- H_0 H_1 ... H_{n-3} Z, one workgroup per block
-//      of columns held in LDS, all reflectors applied in one launch.
+//   4. Back-transformation Z <- H_0 H_1 ... H_{n-3} Z in compact-WY blocks of 8
+//      reflectors, one workgroup per 4 (2, 1 for large n) columns held in LDS,
+//      all blocks in one launch.
 //   5. One first-order orthonormalization of all columns (two FP64 GEMMs): it
 //      restores orthogonality between vectors of close eigenvalues that inverse
 //      iteration did not group.
@@ -269,20 +270,22 @@ __device__ void lu_factor(const double* d, const double* e, int s, int t, double
   L.u3[o] = 0.0;
 }
 
-// Solve in place: x (column g of X over positions [s, t)) <- (T - lam I)^{-1} x.
-// The values each step produces for the next are carried in registers, so the
-// loads of a step depend on nothing written by the one before.
-__device__ void lu_solve(int s, int t, const LuCols& L, int n, int g, double* __restrict__ X, int xcol) {
+// Solve in place: x (column g of X over positions [s, t)) <- (T - lam I)^{-1} (scl x);
+// returns max |x| of the result.  The values each step produces for the next are
+// carried in registers, so the loads of a step depend on nothing written by the
+// one before.
+__device__ double lu_solve(int s, int t, const LuCols& L, int n, int g, double* __restrict__ X, int xcol,
+                           double scl) {
   const double* __restrict__ u1 = L.u1;
   const double* __restrict__ u2 = L.u2;
   const double* __restrict__ u3 = L.u3;
   const double* __restrict__ lm = L.l;
   const double* __restrict__ pv = L.piv;
-  double yi = X[(size_t)s * n + xcol];
+  double yi = X[(size_t)s * n + xcol] * scl;
 #pragma unroll 4
   for (int i = s; i < t - 1; ++i) {
     const size_t o = (size_t)i * n + g;
-    double yn = X[(size_t)(i + 1) * n + xcol];
+    double yn = X[(size_t)(i + 1) * n + xcol] * scl;
     if (pv[o] != 0.0) {
       const double tmp = yi;
       yi = yn;
@@ -294,6 +297,7 @@ __device__ void lu_solve(int s, int t, const LuCols& L, int n, int g, double* __
   }
   X[(size_t)(t - 1) * n + xcol] = yi;
   double x1 = 0.0, x2 = 0.0;  // the solved X[i + 1], X[i + 2]
+  double mx = 0.0;
 #pragma unroll 4
   for (int i = t - 1; i >= s; --i) {
     const size_t o = (size_t)i * n + g;
@@ -302,9 +306,11 @@ __device__ void lu_solve(int s, int t, const LuCols& L, int n, int g, double* __
     if (i + 2 < t) v -= u3[o] * x2;
     v = v / u1[o];
     X[(size_t)i * n + xcol] = v;
+    mx = fmax(mx, fabs(v));
     x2 = x1;
     x1 = v;
   }
+  return mx;
 }
 
 // Group leaders (first eigenvalue of a near-degenerate run inside a block) compute
@@ -343,86 +349,179 @@ __global__ void tridiag_inverse_iteration(int n, const double* d, const double* 
     // eigenvalues of a group are spread by a few ulps so that the factors differ
     const double lq = lam[q] + (double)(q - g) * 4.0 * DBL_EPSILON * nrm;
     lu_factor(d, e, s, t, lq, tiny, L, n, g);
+    // the solves and the orthogonalization are linear, so between iterations the
+    // vector is only rescaled against overflow (by 1 / max |x|, applied as the
+    // next solve loads it); it is normalized once at the end
+    double scl = 1.0;
     for (int it = 0; it < 4; ++it) {
-      lu_solve(s, t, L, n, g, X, q);
-      // orthogonalize against earlier vectors of the group (twice for stability)
-      for (int pass = 0; pass < 2; ++pass) {
-        for (int r = g; r < q; ++r) {
-          double dp = 0.0;
-          for (int i = s; i < t; ++i) dp += X[(size_t)i * n + r] * X[(size_t)i * n + q];
-          for (int i = s; i < t; ++i) X[(size_t)i * n + q] -= dp * X[(size_t)i * n + r];
+      double mx = lu_solve(s, t, L, n, g, X, q, scl);
+      if (q > g) {
+        // orthogonalize against earlier (unit) vectors of the group, twice for stability
+        mx = 0.0;
+        for (int pass = 0; pass < 2; ++pass) {
+          for (int r = g; r < q; ++r) {
+            double dp = 0.0;
+            for (int i = s; i < t; ++i) dp += X[(size_t)i * n + r] * X[(size_t)i * n + q];
+            for (int i = s; i < t; ++i) {
+              const double y = X[(size_t)i * n + q] - dp * X[(size_t)i * n + r];
+              X[(size_t)i * n + q] = y;
+              if (pass == 1 && r == q - 1) mx = fmax(mx, fabs(y));
+            }
+          }
         }
       }
-      // overflow-safe normalization
-      double mx = 0.0;
-      for (int i = s; i < t; ++i) mx = fmax(mx, fabs(X[(size_t)i * n + q]));
       if (!(mx > 0.0) || !isfinite(mx)) {
         atomicExch(status, 1);
         return;
       }
-      double nx = 0.0;
-      const double inv_mx = 1.0 / mx;
-      for (int i = s; i < t; ++i) {
-        const double y = X[(size_t)i * n + q] * inv_mx;
-        nx += y * y;
-      }
-      const double inv = inv_mx / sqrt(nx);
-      for (int i = s; i < t; ++i) X[(size_t)i * n + q] *= inv;
+      scl = 1.0 / mx;
     }
+    double nx = 0.0;
+    for (int i = s; i < t; ++i) {
+      const double y = X[(size_t)i * n + q] * scl;
+      nx += y * y;
+    }
+    const double inv = scl / sqrt(nx);
+    for (int i = s; i < t; ++i) X[(size_t)i * n + q] *= inv;
   }
 }
 
 // ------------------------------------------------------------ back-transform
-// Z <- H_0 ... H_{n-3} Z for a block of `cw` columns held in LDS.
-__global__ __launch_bounds__(256) void tridiag_backtransform(int n, const double* Vs, const double* tau,
-                                                             double* Z, int cw) {
-  extern __shared__ double zs[];  // [n][cw]
-  __shared__ double part[4][8];
-  const int c0 = blockIdx.x * cw;
-  const int ncol = min(cw, n - c0);
-  for (int idx = threadIdx.x; idx < n * cw; idx += blockDim.x) {
-    const int r = idx / cw, c = idx % cw;
+// Z <- H_0 H_1 ... H_{n-3} Z with H_k = I - tau_k v_k v_k^T (v_k: 1 at row k + 1,
+// Vs[k][.] below it), applied in compact-WY blocks of WY_NB reflectors: for the
+// block k0 .. k0 + WY_NB - 1, H_k0 ... H_{k0+WY_NB-1} = I - V T V^T with T upper
+// triangular (T_cc = tau_c, T[0:c, c] = -tau_c T[0:c, 0:c] V[:, 0:c]^T v_c), and the
+// blocks go from the last to the first: Z <- Z - V (T (V^T Z)).
+constexpr int WY_NB = 8;
+
+// V[i][j] of block k0 (row i of the full vector of reflector k0 + j), 0 outside
+__device__ inline double wy_v(const double* Vs, int n, int k0, int nr, int i, int j) {
+  const int k = k0 + j;
+  return (j < nr && i > k) ? Vs[(size_t)k * n + (i - k - 1)] : 0.0;
+}
+
+// One workgroup per block: S = V^T V (upper triangle) by a pass over the rows,
+// then T by the forward recurrence (one thread).  T: [nblk][WY_NB][WY_NB].
+__global__ __launch_bounds__(256) void wy_build_t(int n, const double* Vs, const double* tau, double* Tout) {
+  constexpr int NS = WY_NB * (WY_NB + 1) / 2;
+  __shared__ double part[4][NS];
+  __shared__ double S[WY_NB][WY_NB];
+  const int b = blockIdx.x, k0 = b * WY_NB;
+  const int nr = min(WY_NB, n - 2 - k0);  // reflectors 0 .. n - 3
+  double acc[NS];
+#pragma unroll
+  for (int q = 0; q < NS; ++q) acc[q] = 0.0;
+  for (int i = k0 + 1 + threadIdx.x; i < n; i += blockDim.x) {
+    double v[WY_NB];
+#pragma unroll
+    for (int j = 0; j < WY_NB; ++j) v[j] = wy_v(Vs, n, k0, nr, i, j);
+    int q = 0;
+#pragma unroll
+    for (int l = 0; l < WY_NB; ++l)
+#pragma unroll
+      for (int c = l; c < WY_NB; ++c) acc[q++] += v[l] * v[c];
+  }
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < NS; ++q) {
+    const double t = wave_sum(acc[q]);
+    if (lane == 0) part[w][q] = t;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int q = 0;
+    for (int l = 0; l < WY_NB; ++l)
+      for (int c = l; c < WY_NB; ++c, ++q) S[l][c] = (part[0][q] + part[1][q]) + (part[2][q] + part[3][q]);
+    double T[WY_NB][WY_NB];
+    for (int c = 0; c < WY_NB; ++c) {
+      const double tc = c < nr ? tau[k0 + c] : 0.0;
+      for (int i = 0; i < WY_NB; ++i) T[i][c] = 0.0;
+      T[c][c] = tc;
+      for (int i = 0; i < c; ++i) {
+        double sum = 0.0;
+        for (int l = i; l < c; ++l) sum += T[i][l] * S[l][c];
+        T[i][c] = -tc * sum;
+      }
+    }
+    double* To = Tout + (size_t)b * WY_NB * WY_NB;
+    for (int i = 0; i < WY_NB; ++i)
+      for (int c = 0; c < WY_NB; ++c) To[i * WY_NB + c] = T[i][c];
+  }
+}
+
+// One workgroup per WY_CW columns of Z, held in LDS; the blocks of reflectors in
+// reverse order, two barriers per block.
+template <int WY_CW>
+__global__ __launch_bounds__(256) void tridiag_backtransform(int n, const double* Vs, const double* Tall,
+                                                             double* Z) {
+  extern __shared__ double zs[];  // [n][WY_CW]
+  __shared__ double part[4][WY_NB * WY_CW];
+  __shared__ double Wsh[WY_NB][WY_CW];
+  const int c0 = blockIdx.x * WY_CW;
+  const int ncol = min(WY_CW, n - c0);
+  for (int idx = threadIdx.x; idx < n * WY_CW; idx += blockDim.x) {
+    const int r = idx / WY_CW, c = idx % WY_CW;
     zs[idx] = (c < ncol) ? Z[(size_t)r * n + c0 + c] : 0.0;
   }
   __syncthreads();
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  for (int k = n - 3; k >= 0; --k) {
-    const double t = tau[k];
-    if (t == 0.0) continue;
-    const int m = n - k - 1;
-    const double* v = Vs + (size_t)k * n;
-    double acc[8];
+  const int nblk = (n - 2 + WY_NB - 1) / WY_NB;
+  for (int b = nblk - 1; b >= 0; --b) {
+    const int k0 = b * WY_NB, nr = min(WY_NB, n - 2 - k0);
+    // P = V^T Z over the rows below k0
+    double acc[WY_NB][WY_CW];
 #pragma unroll
-    for (int c = 0; c < 8; ++c) acc[c] = 0.0;
-    for (int i = threadIdx.x; i < m; i += blockDim.x) {
-      const double vi = v[i];
-      const double* zr = zs + (size_t)(k + 1 + i) * cw;
+    for (int j = 0; j < WY_NB; ++j)
 #pragma unroll
-      for (int c = 0; c < 8; ++c)
-        if (c < cw) acc[c] += vi * zr[c];
-    }
+      for (int c = 0; c < WY_CW; ++c) acc[j][c] = 0.0;
+    for (int i = k0 + 1 + threadIdx.x; i < n; i += blockDim.x) {
+      const double* zr = zs + (size_t)i * WY_CW;
 #pragma unroll
-    for (int c = 0; c < 8; ++c) {
-      if (c < cw) {
-        double sv = wave_sum(acc[c]);
-        if (lane == 0) part[w][c] = sv;
+      for (int j = 0; j < WY_NB; ++j) {
+        const double v = wy_v(Vs, n, k0, nr, i, j);
+#pragma unroll
+        for (int c = 0; c < WY_CW; ++c) acc[j][c] += v * zr[c];
       }
     }
+#pragma unroll
+    for (int j = 0; j < WY_NB; ++j)
+#pragma unroll
+      for (int c = 0; c < WY_CW; ++c) {
+        const double t = wave_sum(acc[j][c]);
+        if (lane == 0) part[w][j * WY_CW + c] = t;
+      }
     __syncthreads();
-    double sc[8];
+    // W = T P (T upper triangular)
+    if (threadIdx.x < WY_NB * WY_CW) {
+      const int j = threadIdx.x / WY_CW, c = threadIdx.x % WY_CW;
+      const double* T = Tall + (size_t)b * WY_NB * WY_NB;
+      double sum = 0.0;
+      for (int l = j; l < WY_NB; ++l) {
+        const int q = l * WY_CW + c;
+        sum += T[j * WY_NB + l] * ((part[0][q] + part[1][q]) + (part[2][q] + part[3][q]));
+      }
+      Wsh[j][c] = sum;
+    }
+    __syncthreads();
+    // Z -= V W
+    for (int i = k0 + 1 + threadIdx.x; i < n; i += blockDim.x) {
+      double* zr = zs + (size_t)i * WY_CW;
+      double u[WY_CW];
 #pragma unroll
-    for (int c = 0; c < 8; ++c) sc[c] = (c < cw) ? t * ((part[0][c] + part[1][c]) + (part[2][c] + part[3][c])) : 0.0;
-    for (int i = threadIdx.x; i < m; i += blockDim.x) {
-      const double vi = v[i];
-      double* zr = zs + (size_t)(k + 1 + i) * cw;
+      for (int c = 0; c < WY_CW; ++c) u[c] = 0.0;
 #pragma unroll
-      for (int c = 0; c < 8; ++c)
-        if (c < cw) zr[c] -= vi * sc[c];
+      for (int j = 0; j < WY_NB; ++j) {
+        const double v = wy_v(Vs, n, k0, nr, i, j);
+#pragma unroll
+        for (int c = 0; c < WY_CW; ++c) u[c] += v * Wsh[j][c];
+      }
+#pragma unroll
+      for (int c = 0; c < WY_CW; ++c) zr[c] -= u[c];
     }
     __syncthreads();
   }
-  for (int idx = threadIdx.x; idx < n * cw; idx += blockDim.x) {
-    const int r = idx / cw, c = idx % cw;
+  for (int idx = threadIdx.x; idx < n * WY_CW; idx += blockDim.x) {
+    const int r = idx / WY_CW, c = idx % WY_CW;
     if (c < ncol) Z[(size_t)r * n + c0 + c] = zs[idx];
   }
 }
@@ -524,6 +623,7 @@ size_t eigh_workspace_bytes(int n) {
   add((size_t)n * 8 * 5);  // tau d e p lam
   add((size_t)n * 4 * 3 + 64);  // blk_start blk_end rank status
   add(64);          // tnorm
+  add((size_t)((n + WY_NB - 1) / WY_NB + 1) * WY_NB * WY_NB * 8);  // compact-WY T factors
   return b;
 }
 
@@ -552,6 +652,7 @@ int eigh_run(const double* A_in, int n, double* w_out, double* Z_out, char* ws, 
   int* rank = blk_end + n;
   int* status = rank + n;
   double* tnorm = (double*)take(64);
+  double* Tall = (double*)take((size_t)((n + WY_NB - 1) / WY_NB + 1) * WY_NB * WY_NB * 8);
   hipError_t err;
   ProfScope prof_all(DFPT2_STAGE_EIGH, st);
   if ((err = hipMemcpyAsync(A, A_in, nn * 8, hipMemcpyDeviceToDevice, st)) != hipSuccess)
@@ -582,13 +683,18 @@ int eigh_run(const double* A_in, int n, double* w_out, double* Z_out, char* ws, 
   }
   hipLaunchKernelGGL(tridiag_inverse_iteration, dim3((n + 63) / 64), dim3(64), 0, st, n, d, e, blk_start, blk_end,
                      tnorm, lam, L, X, status, floor_ptr);
-  // 4. back-transformation
+  // 4. back-transformation (compact-WY blocks)
   if (n > 2) {
-    int cw = 8;
+    int cw = 4;  // columns per workgroup: as many as the LDS holds, up to 4
     while (cw > 1 && (size_t)n * cw * 8 > 150 * 1024) cw >>= 1;
     if ((size_t)n * cw * 8 > 150 * 1024) return fail(DFPT2_ERR_UNSUPPORTED, "eigh: n=%d too large", n);
-    hipLaunchKernelGGL(tridiag_backtransform, dim3((n + cw - 1) / cw), dim3(256), (size_t)n * cw * 8, st, n, Vs,
-                       tau, X, cw);
+    const int nblk = (n - 2 + WY_NB - 1) / WY_NB;
+    hipLaunchKernelGGL(wy_build_t, dim3(nblk), dim3(256), 0, st, n, Vs, tau, Tall);
+    const dim3 grid((n + cw - 1) / cw), block(256);
+    const size_t lds = (size_t)n * cw * 8;
+    if (cw == 4) hipLaunchKernelGGL(tridiag_backtransform<4>, grid, block, lds, st, n, Vs, Tall, X);
+    else if (cw == 2) hipLaunchKernelGGL(tridiag_backtransform<2>, grid, block, lds, st, n, Vs, Tall, X);
+    else hipLaunchKernelGGL(tridiag_backtransform<1>, grid, block, lds, st, n, Vs, Tall, X);
   }
   // 5. one first-order orthonormalization of all columns: with G = Z^T Z = I + E
   //    and E small, Z <- Z (I - U), U = strict upper part of E + diag(E) / 2, leaves
