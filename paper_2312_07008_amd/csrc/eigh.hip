@@ -2,9 +2,10 @@
 // Eq. 8 (Gamma V = n V) and for the recanonicalization of the kept space.
 //
 //   1. Householder reduction to tridiagonal form, one column per step on the
-//      full symmetric matrix: a kernel that forms the reflector (redundantly in
-//      every workgroup) and p = tau A v, then a kernel for the rank-2 update
-//      A -= v w^T + w v^T with w = p - (tau/2)(p.v) v.
+//      full symmetric matrix: the reflector (formed redundantly in every
+//      workgroup), p = tau A v and the rank-2 update A -= v w^T + w v^T with
+//      w = p - (tau/2)(p.v) v.  Up to n = 2731 one launch per column applies the
+//      previous column's update lazily while forming p; above, two launches.
 //   2. Splitting at negligible off-diagonal entries, then every eigenvalue by
 //      multisection on Sturm counts (one wave per eigenvalue, 64 points a round).
 //   3. Eigenvectors of the tridiagonal matrix by inverse iteration with a
@@ -110,6 +111,94 @@ __global__ __launch_bounds__(256) void tridiag_step_b(double* A, int n, int k, c
     double* a = A + (size_t)(k + 1 + r) * n + (k + 1 + c);
     *a -= vr * wc + wr * vc;
   }
+}
+
+// ---------------------------------------------------------------- fused step
+// Column k with the rank-2 update of column k - 1 applied lazily: the update
+// A -= v' w'^T + w' v'^T of column k - 1 (over indices k .. n - 1; w' = p' -
+// (tau'/2)(p'.v') v' rebuilt here from p' = p of column k - 1) is applied to row k
+// on the fly (it gives the reflector and d[k]) and, row by row, to the trailing
+// block k + 1 .. n - 1, which is stored back and multiplied by v_k in the same
+// pass: one launch per column instead of two, and each trailing row read and
+// written once.  v', w' and v_k are staged in LDS ((3 m + 2) doubles, m = n - k - 1).
+__global__ __launch_bounds__(256) void tridiag_step_lazy(double* A, int n, int k, double* Vs, double* tau,
+                                                         double* d, double* e, const double* p_prev,
+                                                         double* p_out) {
+  extern __shared__ double sh[];
+  const int m = n - k - 1;
+  double* vsh = sh;           // v_k: m
+  double* vpr = sh + m;       // v': m + 1 (index k + i)
+  double* wpr = vpr + m + 1;  // w': m + 1
+  __shared__ double red[8];
+  if (k > 0) {  // workgroup-uniform
+    const double* vp = Vs + (size_t)(k - 1) * n;
+    double dot = 0.0;
+    for (int i = threadIdx.x; i <= m; i += blockDim.x) dot += p_prev[i] * vp[i];
+    dot = block_sum(dot, red);
+    const double K = 0.5 * tau[k - 1] * dot;
+    for (int i = threadIdx.x; i <= m; i += blockDim.x) {
+      vpr[i] = vp[i];
+      wpr[i] = p_prev[i] - K * vp[i];
+    }
+  } else {
+    for (int i = threadIdx.x; i <= m; i += blockDim.x) vpr[i] = wpr[i] = 0.0;
+  }
+  __syncthreads();
+  const double v0 = vpr[0], w0 = wpr[0];
+  const double* rowk = A + (size_t)k * n + (k + 1);
+  double s2 = 0.0;
+  for (int i = 1 + threadIdx.x; i < m; i += blockDim.x) {
+    const double x = rowk[i] - (v0 * wpr[1 + i] + w0 * vpr[1 + i]);
+    s2 += x * x;
+  }
+  s2 = block_sum(s2, red);
+  const double alpha = rowk[0] - (v0 * wpr[1] + w0 * vpr[1]);
+  double t = 0.0, beta = alpha, scale = 0.0;
+  if (s2 > 0.0) {
+    const double mu = sqrt(alpha * alpha + s2);
+    beta = (alpha > 0.0) ? -mu : mu;
+    t = (beta - alpha) / beta;
+    scale = 1.0 / (alpha - beta);
+  }
+  for (int i = threadIdx.x; i < m; i += blockDim.x)
+    vsh[i] = (i == 0) ? 1.0 : (rowk[i] - (v0 * wpr[1 + i] + w0 * vpr[1 + i])) * scale;
+  __syncthreads();
+  if (blockIdx.x == 0) {
+    for (int i = threadIdx.x; i < m; i += blockDim.x) Vs[(size_t)k * n + i] = vsh[i];
+    if (threadIdx.x == 0) {
+      tau[k] = t;
+      e[k] = beta;
+      d[k] = A[(size_t)k * n + k] - 2.0 * v0 * w0;
+    }
+  }
+  const int lane = threadIdx.x & 63;
+  const int gw = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const int nwaves = gridDim.x * (blockDim.x >> 6);
+  for (int r = gw; r < m; r += nwaves) {
+    double* row = A + (size_t)(k + 1 + r) * n + (k + 1);
+    const double vr = vpr[1 + r], wr = wpr[1 + r];
+    double acc = 0.0;
+    for (int c = lane; c < m; c += 64) {
+      const double a = row[c] - (vr * wpr[1 + c] + wr * vpr[1 + c]);
+      row[c] = a;
+      acc += a * vsh[c];
+    }
+    acc = wave_sum(acc);
+    if (lane == 0) p_out[r] = t * acc;
+  }
+}
+
+// d[n-2], d[n-1], e[n-2] from the last 2 x 2 block, with the update of column n - 3
+// still pending when the lazy steps were used (p_last = p of column n - 3)
+__global__ void tridiag_tail_lazy(const double* A, int n, const double* Vs, const double* tau,
+                                  const double* p_last, double* d, double* e) {
+  if (threadIdx.x != 0) return;
+  const double* v = Vs + (size_t)(n - 3) * n;  // entries 0, 1 <-> indices n - 2, n - 1
+  const double K = 0.5 * tau[n - 3] * (p_last[0] * v[0] + p_last[1] * v[1]);
+  const double w0 = p_last[0] - K * v[0], w1 = p_last[1] - K * v[1];
+  d[n - 2] = A[(size_t)(n - 2) * n + (n - 2)] - 2.0 * v[0] * w0;
+  d[n - 1] = A[(size_t)(n - 1) * n + (n - 1)] - 2.0 * v[1] * w1;
+  e[n - 2] = A[(size_t)(n - 1) * n + (n - 2)] - (v[1] * w0 + w1 * v[0]);
 }
 
 __global__ void tridiag_tail(const double* A, int n, double* d, double* e) {
@@ -658,18 +747,31 @@ int eigh_run(const double* A_in, int n, double* w_out, double* Z_out, char* ws, 
   if ((err = hipMemcpyAsync(A, A_in, nn * 8, hipMemcpyDeviceToDevice, st)) != hipSuccess)
     return hip_fail(err, "eigh copy");
   hipLaunchKernelGGL(zero_int, dim3(1), dim3(64), 0, st, status, 1);
-  // 1. tridiagonalization
-  for (int k = 0; k + 2 < n; ++k) {
-    const int m = n - k - 1;
-    int ga = (m + 3) / 4;
-    if (ga > 512) ga = 512;
-    hipLaunchKernelGGL(tridiag_step_a, dim3(ga), dim3(256), (size_t)m * 8, st, A, n, k, Vs, tau, d, e, p);
-    int gx = (m + 255) / 256;
-    int gy = (m + 15) / 16;
-    if (gy > 256) gy = 256;
-    hipLaunchKernelGGL(tridiag_step_b, dim3(gx, gy), dim3(256), 0, st, A, n, k, Vs, tau, p);
+  // 1. tridiagonalization: one lazy-update launch per column where its LDS
+  //    staging fits in 64 KB, else the two-launch form
+  if (n >= 3 && (size_t)(3 * (n - 1) + 2) * 8 <= 64 * 1024) {
+    double* pb[2] = {p, lam};  // p of consecutive columns alternate (lam is free until step 2)
+    for (int k = 0; k + 2 < n; ++k) {
+      const int m = n - k - 1;
+      int ga = (m + 3) / 4;
+      if (ga > 512) ga = 512;
+      hipLaunchKernelGGL(tridiag_step_lazy, dim3(ga), dim3(256), (size_t)(3 * m + 2) * 8, st, A, n, k, Vs, tau, d,
+                         e, pb[(k + 1) & 1], pb[k & 1]);
+    }
+    hipLaunchKernelGGL(tridiag_tail_lazy, dim3(1), dim3(64), 0, st, A, n, Vs, tau, pb[(n - 3) & 1], d, e);
+  } else {
+    for (int k = 0; k + 2 < n; ++k) {
+      const int m = n - k - 1;
+      int ga = (m + 3) / 4;
+      if (ga > 512) ga = 512;
+      hipLaunchKernelGGL(tridiag_step_a, dim3(ga), dim3(256), (size_t)m * 8, st, A, n, k, Vs, tau, d, e, p);
+      int gx = (m + 255) / 256;
+      int gy = (m + 15) / 16;
+      if (gy > 256) gy = 256;
+      hipLaunchKernelGGL(tridiag_step_b, dim3(gx, gy), dim3(256), 0, st, A, n, k, Vs, tau, p);
+    }
+    hipLaunchKernelGGL(tridiag_tail, dim3(1), dim3(64), 0, st, A, n, d, e);
   }
-  hipLaunchKernelGGL(tridiag_tail, dim3(1), dim3(64), 0, st, A, n, d, e);
   // 2. split + bisection
   hipLaunchKernelGGL(tridiag_split, dim3(1), dim3(64), 0, st, n, d, e, blk_start, blk_end, tnorm);
   hipLaunchKernelGGL(tridiag_multisect, dim3((n + 3) / 4), dim3(256), 0, st, n, d, e, blk_start, blk_end, tnorm,
