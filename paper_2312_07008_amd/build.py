@@ -31,7 +31,6 @@ SOURCES = [
     "ladder.cpp",
     "active_particle.hip",
     "split.hip",
-    "pair_bf16.hip",
     "pair_bf16_v.hip",
     "pair_fp8.hip",
     "pair_i8.hip",

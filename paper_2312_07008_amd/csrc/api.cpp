@@ -65,7 +65,10 @@ int plan_pass(const dfpt2_opts* o, PassPlan* pl, bool energy_only) {
   p.n_up = p.n_core * (p.n_core + 1) / 2;
   const size_t mat = (size_t)p.n_v * p.n_v;
   int64_t batch = o->pair_batch;
-  if (energy_only) batch = 65535;
+  // energy-only passes store no amplitudes: one batch of every pair, except with
+  // BF16 slices, whose product writes V to a buffer of one batch for the epilogue
+  const bool v_buffer = energy_only && o->precision == DFPT2_BF16_SLICED;
+  if (energy_only && !v_buffer) batch = 65535;
   if (batch == 0) {
     const double cap_bytes = 8.0e9;
     batch = (int64_t)(cap_bytes / (double)(mat * sizeof(double)));
@@ -137,7 +140,7 @@ int plan_pass(const dfpt2_opts* o, PassPlan* pl, bool energy_only) {
   };
   p.off_pairs = take(sizeof(int2) * (size_t)(p.n_up > 0 ? p.n_up : 1));
   p.off_count = take(sizeof(int) * 4);
-  p.off_T = take(energy_only ? 0 : sizeof(double) * mat * p.batch);
+  p.off_T = take(energy_only && !v_buffer ? 0 : sizeof(double) * mat * p.batch);  // T, or V of energy-only BF16
   p.off_epart = take(sizeof(double) * (size_t)p.batch * p.nTP1);
   p.off_tpart = take(sizeof(double) * (size_t)p.batch * p.nTP1);
   p.off_pe = take(sizeof(double) * 2 * (size_t)(p.n_up > 0 ? p.n_up : 1));
@@ -287,9 +290,15 @@ hipError_t launch_pair(const PairLaunch& L, const PairKernelArgs& a, int n_pairs
     if (e != hipSuccess) return e;
     if (product) product->close();
     ProfScope ps(DFPT2_STAGE_PAIR_EPILOGUE, st);
-    return launch_pair_epi_bf16(b, n_pairs, st);
+    return launch_pair_epi_bf16(b, n_pairs, true, st);
   }
-  return launch_pair_gemm_bf16(b, L.ns, n_pairs, st);
+  if (L.vbuf) {  // energy only, with a V buffer: the same two kernels, nothing stored
+    b.T = L.vbuf;
+    const hipError_t e = launch_pair_v_bf16(b, L.ns, n_pairs, st);
+    if (e != hipSuccess) return e;
+    return launch_pair_epi_bf16(b, n_pairs, false, st);
+  }
+  return hipErrorInvalidValue;  // BF16 needs amplitudes to store or a V buffer
 }
 
 // Active blocks of the pass (row a6): core-active pairs in batches of cores, then
@@ -435,6 +444,7 @@ int run_pass(const PassPlan& pl, const dfpt2_opts& o, const double* eps_h, const
   const size_t mat = (size_t)pl.n_v * pl.n_v;
 
   PairLaunch L{pl.precision, pl.ns1, B, nullptr, nullptr, nullptr, pl.n_v_pad, pl.n_aux_pad, nullptr};
+  if (pl.energy_only && pl.precision == DFPT2_BF16_SLICED) L.vbuf = reinterpret_cast<double*>(ws + pl.off_T);
   if (pl.precision != DFPT2_FP64) {
     ProfScope ps(DFPT2_STAGE_SPLIT, s);
     double* nrm = reinterpret_cast<double*>(ws + pl.off_norm2);

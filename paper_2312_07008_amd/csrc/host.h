@@ -62,6 +62,7 @@ struct PairLaunch {
   const int* rexp;  // INT8 row exponents
   int n_v_pad, n_aux_pad;
   const double* norm2;
+  double* vbuf = nullptr;  // BF16 energy-only passes: V of one batch for the epilogue kernel
 };
 class ProfScope;
 // `product` (may be null): the caller's timer of the pair product; where the

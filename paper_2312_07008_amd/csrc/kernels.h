@@ -46,11 +46,11 @@ struct PairSlicedArgs {
   double s;
   double e_weight;
 };
-hipError_t launch_pair_gemm_bf16(const PairSlicedArgs& a, int ns, int n_pairs, hipStream_t st);
 // the same pass as two kernels (pair_bf16_v.hip): the product V into a.T (slabs of a
 // multiple of 128 rows), then the epilogue, which overwrites V in a.T with T
+// (store) or only forms the energy partials (!store)
 hipError_t launch_pair_v_bf16(const PairSlicedArgs& a, int ns, int n_pairs, hipStream_t st);
-hipError_t launch_pair_epi_bf16(const PairSlicedArgs& a, int n_pairs, hipStream_t st);
+hipError_t launch_pair_epi_bf16(const PairSlicedArgs& a, int n_pairs, bool store, hipStream_t st);
 hipError_t launch_pair_gemm_fp8(const PairSlicedArgs& a, int ns, int n_pairs, hipStream_t st);
 hipError_t launch_pair_gemm_i8(const PairSlicedArgs& a, int ns, int n_pairs, hipStream_t st);
 // largest n_aux_pad for which the INT8 level sums stay exact with ns digits

@@ -1,31 +1,63 @@
-// Split-BF16 pair product in two kernels, for passes that store the amplitudes:
+// Split-BF16 pair product V = B_i B_j^T and the DSRG epilogue (paper App. A,
+// Eq. A7), in two kernels:
 //
 //   pair_v_bf16_kernel    V^{ij} = B_i B_j^T over 128 x 64 tiles of the full
-//                         n_v x n_v matrix, written in FP64 into the amplitude
-//                         buffer T[p] (same slices, levels and exact FP32 level
-//                         sums as pair_bf16.hip);
+//                         n_v x n_v matrix, written in FP64 into a buffer of one
+//                         batch (the amplitude buffer T[p] when the pass stores
+//                         amplitudes);
 //   pair_epi_bf16_kernel  per 64 x 64 tile pair (I <= J), V[I,J] and V[J,I]^T
 //                         read back into the MFMA register layout, then the
-//                         fused DSRG regularizer / energy / density-row epilogue
-//                         of pair_epilogue.h (paper App. A, Eq. A7), which
-//                         overwrites V with T in place.
+//                         regularizer / energy / density-row epilogue of
+//                         pair_epilogue.h, which (STORE) overwrites V with T in
+//                         place, or (energy-only passes) only forms the energy
+//                         and norm partials.
 //
-// The fused kernel (pair_bf16.hip) computes V^{ij}[I,J] and V^{ji}[I,J] in one
-// workgroup so that the exchange partner of every element is lane-local; that
-// fixes its tile at 64 x 64 per product.  Its time is set by the bytes the
-// direct loads request (L2 hits and misses), so here the product runs on its own
-// with a 128 x 64 tile, a quarter fewer bytes per flop, at the cost of one FP64
-// write and two FP64 reads of V per element (a few ms per batch).  Measured
-// on the 80-core, 1200-virtual, 4000-auxiliary workload: 58.6 ms per batch of
-// 512 pairs for both kernels against 62.6 ms fused; 128 x 128 tiles (8 waves,
-// one workgroup per CU) 59.9 ms, 128 x 32 tiles (2 waves) 80.1 ms.
+// Operands come from split.hip: each FP64 row of B is sum_t slice_t with
+// slice_t an 8-bit integer times 2^(E - 8 - 9(t-1)).  The product of two rows
+// is sum_{s,t} slice_s(a) . slice_t(b); terms with s + t - 1 = L form level L,
+// of magnitude 2^-9(L-1) relative to level 1.  With NS slices the kernel keeps
+// the levels L <= NS (NS (NS+1)/2 products; NS = 4 leaves a relative error near
+// 2^-34 per element).
+//
+// Accumulation: level-1 and level-2 products are integer multiples of one unit
+// per output element, at most 2^16 units each, so FP32 MFMA sums of 128
+// contraction steps (one product per step at level 1, two at level 2) stay at or
+// below 2^24 units and are exact.  These two accumulators are added into FP64
+// every 128 steps.  Levels >= 3 carry 2^-18 of the value or less and are summed
+// in FP32 over the whole contraction; their rounding stays far below the
+// slicing error.  For i == j the epilogue replaces the diagonal V^{ii}_{aa} by
+// ||B_ia||^2 from an FP64 norm computed while splitting: the dropped slice
+// products (t, t) there are sums of squares, i.e. biased, and the diagonal
+// carries a large share of E.
+//
+// Why two kernels: a fused kernel (the FP64, FP8 and INT8 pair kernels) computes
+// V^{ij}[I,J] and V^{ji}[I,J] in one workgroup so that the exchange partner of
+// every element is lane-local, which fixes its tile at 64 x 64 per product.  The
+// time of these kernels is set by the bytes the direct loads request (L2 hits and
+// misses), so here the product runs on its own with a 128 x 64 tile, a quarter
+// fewer bytes per flop, at the cost of one FP64 write and two FP64 reads of V
+// per element (a few ms per batch).  Measured on the 80-core, 1200-virtual,
+// 4000-auxiliary workload: 58.6 ms per batch of 512 pairs for both kernels
+// against 62.6 ms for the fused BF16 kernel this replaced; 128 x 128 tiles (8
+// waves, one workgroup per CU) 59.9 ms, 128 x 32 tiles (2 waves) 80.1 ms.
 //
 // Tile of the V kernel: 4 waves, wave (wr, wc) owns rows 64 wr .. 64 wr + 63
 // (two 32 x 32 MFMA blocks) and columns 32 wc .. 32 wc + 31; two workgroups per
-// CU.  Staging as in pair_bf16.hip: 16-wide contraction chunks of a 128-row and
-// a 64-row panel go from global memory straight into LDS (XOR-swizzled 128-byte
-// rows), double buffered; every wave moves 6 of the 24 kilobytes of a chunk.
-// The slabs must have a multiple of 128 rows.
+// CU.  Staging: 16-wide contraction chunks of a 128-row and a 64-row panel go
+// from global memory straight into LDS (global_load_lds, 16 bytes per lane, no
+// register round trip), double buffered; every wave moves 6 of the 24 kilobytes
+// of a chunk.  One LDS row holds the chunk of one virtual: 8 slots of 16 bytes
+// (slice t, half h -> slot 2t + h; slots >= 2 NS are padding), XOR-swizzled by
+// f(r) = (r ^ (r >> 3)) & 7 so that the fragment reads (eight or sixteen
+// consecutive rows, one logical slot) hit distinct banks and each direct load
+// fills one contiguous kilobyte (8 rows x 8 slots) with no conflict.  The slabs
+// must have a multiple of 128 rows.
+//
+// Block order: the hardware deals consecutive workgroups round-robin to the 8
+// XCDs, each with its own L2.  The launch is 1-D and the block index is remapped
+// so that every XCD walks a contiguous range of (pair, tile) in order: the
+// workgroups resident on one XCD then belong to one or two pairs and share the
+// same slabs B_i, B_j through that XCD's L2.
 #include "common.h"
 #include "kernels.h"
 #include "pair_epilogue.h"
@@ -173,7 +205,9 @@ __global__ __launch_bounds__(128 * WC, 4 / WC) void pair_v_bf16_kernel(PairSlice
   }
 }
 
-// Epilogue pass over 64 x 64 tile pairs (I <= J) of the V written above.
+// Epilogue pass over 64 x 64 tile pairs (I <= J) of the V written above; without
+// STORE (energy-only passes) only the energy and norm partials are formed.
+template <bool STORE>
 __global__ __launch_bounds__(256) void pair_epi_bf16_kernel(PairSlicedArgs a) {
   __shared__ double scratch[272];
   const int L = xcd_block_v(blockIdx.x, a.nTP * a.n_blk_pairs);
@@ -199,7 +233,7 @@ __global__ __launch_bounds__(256) void pair_epi_bf16_kernel(PairSlicedArgs a) {
     for (int r = 0; r < 16; ++r) dQ[r] = dP[r];
   }
   __syncthreads();  // every read of this tile pair's V precedes the T written over it
-  sliced_pair_epilogue<true>(a, p, tp, I, J, pr.x, pr.y, dP, dQ, scratch);
+  sliced_pair_epilogue<STORE>(a, p, tp, I, J, pr.x, pr.y, dP, dQ, scratch);
 }
 
 hipError_t launch_pair_v_bf16(const PairSlicedArgs& a, int ns, int n_pairs, hipStream_t st) {
@@ -220,12 +254,13 @@ hipError_t launch_pair_v_bf16(const PairSlicedArgs& a, int ns, int n_pairs, hipS
   return hipGetLastError();
 }
 
-hipError_t launch_pair_epi_bf16(const PairSlicedArgs& a, int n_pairs, hipStream_t st) {
+hipError_t launch_pair_epi_bf16(const PairSlicedArgs& a, int n_pairs, bool store, hipStream_t st) {
   if (n_pairs <= 0) return hipSuccess;
   if (!a.T || (long long)a.nTP * n_pairs > 0x7fffffffLL) return hipErrorInvalidValue;
   PairSlicedArgs b = a;
   b.n_blk_pairs = n_pairs;
-  hipLaunchKernelGGL(pair_epi_bf16_kernel, dim3(a.nTP * n_pairs), dim3(256), 0, st, b);
+  if (store) hipLaunchKernelGGL(pair_epi_bf16_kernel<true>, dim3(a.nTP * n_pairs), dim3(256), 0, st, b);
+  else hipLaunchKernelGGL(pair_epi_bf16_kernel<false>, dim3(a.nTP * n_pairs), dim3(256), 0, st, b);
   return hipGetLastError();
 }
 

@@ -1,4 +1,4 @@
-// Epilogue shared by the sliced pair kernels (BF16 slices in pair_bf16.hip,
+// Epilogue shared by the sliced pair kernels (BF16 slices in pair_bf16_v.hip,
 // INT8 digits in pair_i8.hip): once a workgroup holds P = V^{ij}[I,J] and
 // Q = V^{ji}[I,J] of its tile pair in FP64, the DSRG regularizer, amplitudes and
 // energy partials follow the paper's App. A (Eq. A7), exactly as in the FP64 pair

@@ -11,7 +11,7 @@
 // FP32 rounding (relative 2^-24 per accumulation step) on top of the slicing
 // error (relative 2^-(5 NS - 1) of the block maxima).
 //
-// Tiling as in pair_bf16.hip: one workgroup = unordered pair {i <= j} x tile pair
+// Tiling as in pair_f64.hip: one workgroup = unordered pair {i <= j} x tile pair
 // (I <= J) of 64 x 64; every wave owns the same 32 x 32 block of P = V^{ij}[I,J]
 // and of Q = V^{ji}[I,J].  One contraction chunk is 64 wide; an LDS row holds the
 // chunk of one virtual: 16 slots of 16 bytes (slice t, lane half h, quarter q ->

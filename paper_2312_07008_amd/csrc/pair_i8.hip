@@ -17,7 +17,7 @@
 // For i == j the diagonal V^{ii}_{aa} = ||B_ia||^2 comes from the FP64 norm
 // computed while splitting (the dropped digit products there are biased).
 //
-// Tiling and order as in pair_bf16.hip: one workgroup = unordered pair {i <= j}
+// Tiling as in pair_f64.hip, order as in pair_bf16_v.hip: one workgroup = unordered pair {i <= j}
 // x tile pair (I <= J) of 64 x 64, every wave owns the same 32 x 32 block of
 // P = V^{ij}[I,J] and Q = V^{ji}[I,J]; the 1-D launch is remapped so that every
 // XCD walks a contiguous range of (pair, tile pair).

@@ -10,7 +10,7 @@
 // below 2^-90 would push trailing slices into BF16's subnormal range and lose
 // bits.)  Every slice of a row is an integer multiple of that row's unit 2^(E - 8 - 9(t-1)); products of slices from two
 // rows are integer multiples of one common unit, which is what makes the FP32
-// MFMA sums of the leading levels exact (see pair_bf16.hip).
+// MFMA sums of the leading levels exact (see pair_bf16_v.hip).
 // Slices are written true-scale, so a dot product of slices needs no rescaling.
 //
 // The kernel also returns every row's squared norm in FP64.  The pair kernel uses

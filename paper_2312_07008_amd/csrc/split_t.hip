@@ -26,7 +26,7 @@
 // diagonal carries the trace of D.  The density kernel leaves the diagonal out.
 //
 // The four row maxima and the diagonal partial sums come from the pair kernel's
-// epilogue (pair_bf16.hip), which holds every amplitude once.  Here one kernel
+// epilogue (pair_epilogue.h), which holds every amplitude once.  Here one kernel
 // writes the slices and one workgroup per virtual a then sums the diagonal
 // partials in a fixed order.
 #include <cmath>
