@@ -70,3 +70,33 @@ def test_c2_full_size_against_golden():
                                      t["no_vecs"], t["n_kept"], g["raw"]["e_pt2"])
         cc = c["correction"].cpu().numpy()
         assert dd_diff((cc[0], cc[1]), tr["correction"]) <= 1e-8
+
+
+@pytest.mark.parametrize("precision,name", [(1, "bf16"), (3, "int8")])
+def test_c2_mixed_against_golden(precision, name):
+    """c2 through the mixed paths (split BF16, INT8 digits): the active blocks
+    store amplitudes while the core pairs of the kept-space energy run through
+    the energy-only product; energy, occupation numbers, kept counts at the
+    three p_o and the corrections against the oracle's values at the mixed bound
+    (1e-6 Eh)."""
+    dp = need_gpu()
+    with open(os.path.join(HERE, "golden", "c2_s0.5.json")) as f:
+        gold = json.load(f)
+    inp = synth.config_inputs("c2")
+    g = gpu_pass(inp, 0.5, precision=precision)
+    dE = dd_diff(g["energy"], gold["energy"])
+    occ_ref = np.array(gold["occ"])
+    for tr in gold["truncation"]:
+        t = dp.fno_truncate(g["raw"]["D_vv"], tr["p_o"])
+        occ = t["occ"].cpu().numpy()
+        d = g["dev"]
+        c = dp.pt2_energy_correction(g["opts"], d["eps_hole"], d["eps_vir"], d["gamma_act"], d["B"],
+                                     t["no_vecs"], t["n_kept"], g["raw"]["e_pt2"])
+        cc = c["correction"].cpu().numpy()
+        dC = dd_diff((cc[0], cc[1]), tr["correction"])
+        print(f"c2 {name} p_o {tr['p_o']}: dE {dE:.3e}, max dON {np.abs(occ - occ_ref).max():.3e}, "
+              f"kept {t['n_kept']} ({tr['n_kept']}), dcorr {dC:.3e}", flush=True)
+        assert np.abs(occ - occ_ref).max() <= 1e-9 * occ_ref.max()
+        assert t["n_kept"] == tr["n_kept"]
+        assert dC <= 1e-6
+    assert dE <= 1e-6
