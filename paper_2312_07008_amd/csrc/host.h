@@ -84,7 +84,6 @@ class ProfScope {
   hipEvent_t a_;
 };
 void prof_flush();
-bool prof_on();
 
 hipError_t gemm_f64(const double* A, int lda, long long sA, int transA, const double* B, int ldb, long long sB,
                     int transB, double* C, int ldc, long long sC, int M, int N, int K, int batch, double alpha,

@@ -35,8 +35,6 @@ hipEvent_t get_event() {
 }
 }  // namespace
 
-bool prof_on() { return g_prof.on; }
-
 ProfScope::ProfScope(int stage, hipStream_t s) : stage_(stage), s_(s), a_(nullptr) {
   if (!g_prof.on) return;
   a_ = get_event();
