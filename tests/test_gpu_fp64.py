@@ -90,7 +90,8 @@ def _gpu_eigh(A):
 @pytest.mark.parametrize("kind,n", [("random", 1), ("random", 2), ("random", 3), ("random", 97),
                                     ("random", 256), ("identity", 40), ("diag_repeat", 33),
                                     ("blocks", 60), ("psd_lowrank", 120), ("clustered", 80), ("zeros", 5),
-                                    ("zeros", 1), ("random", 1200), ("graded", 300)])
+                                    ("zeros", 1), ("random", 1200), ("graded", 300),
+                                    ("random", 2731), ("random", 2800)])  # last lazy size, two-launch form
 def test_eigh_against_lapack(kind, n):
     rng = np.random.default_rng(n)
     if kind == "random":
