@@ -210,3 +210,16 @@ def test_truncation_rules_c1():
                                  t["n_kept"], g["raw"]["e_pt2"])
     ek = c["e_kept"].cpu().numpy()
     assert dd_diff((ek[0], ek[1]), e_kept) <= E_TOL
+
+
+@pytest.mark.parametrize("precision", [0, 1, 3])
+def test_nonfinite_integral_reported(precision):
+    """A NaN in B (ordinary data to the kernels) reaches the energy through the
+    exact FP64 diagonal norms and is reported as DFPT2_ERR_NONFINITE, for the
+    FP64, split-BF16 and INT8-digit paths."""
+    dp = need_gpu()
+    inp = synth.generate(5, 0, 70, 40, seed=2)
+    inp.B[3, 1, 7] = np.nan  # one element of hole 3's slab
+    with pytest.raises(dp.DfptError) as ei:
+        gpu_pass(inp, 0.5, precision=precision)
+    assert ei.value.status == -5
