@@ -404,7 +404,7 @@ def main():
     kname = {"int8": "i8"}.get(args.precision, args.precision)
     split_epi = prof["pair_epilogue"][1] > 0
     if split_epi:
-        kid, kdesc = f"pair_v_bf16_kernel<{ns1},2>", "pair_v_bf16 (V = B_i B_j^T, 128 x 64 tiles"
+        kid, kdesc = f"pair_v_bf16_kernel<{ns1},4>", "pair_v_bf16 (V = B_i B_j^T, 128 x 128 tiles"
     else:
         kid = f"pair_gemm_{kname}_kernel<{ns1},true>"
         kdesc = f"pair_gemm_{kname if ns1 > 1 else 'f64'} (V = B_i B_j^T with the fused DSRG epilogue"

@@ -1,7 +1,7 @@
 // Split-BF16 pair product V = B_i B_j^T and the DSRG epilogue (paper App. A,
 // Eq. A7), in two kernels:
 //
-//   pair_v_bf16_kernel    V^{ij} = B_i B_j^T over 128 x 64 tiles of the full
+//   pair_v_bf16_kernel    V^{ij} = B_i B_j^T over 128 x 128 tiles of the full
 //                         n_v x n_v matrix, written in FP64 into a buffer of one
 //                         batch (the amplitude buffer T[p] when the pass stores
 //                         amplitudes);
@@ -34,20 +34,23 @@
 // V^{ij}[I,J] and V^{ji}[I,J] in one workgroup so that the exchange partner of
 // every element is lane-local, which fixes its tile at 64 x 64 per product.  The
 // time of these kernels is set by the bytes the direct loads request (L2 hits and
-// misses), so here the product runs on its own with a 128 x 64 tile, a quarter
-// fewer bytes per flop, at the cost of one FP64 write and two FP64 reads of V
-// per element (a few ms per batch).  Measured on the 80-core, 1200-virtual,
-// 4000-auxiliary workload: 58.6 ms per batch of 512 pairs for both kernels
-// against 62.6 ms for the fused BF16 kernel this replaced; 128 x 128 tiles (8
-// waves, one workgroup per CU) 59.9 ms, 128 x 32 tiles (2 waves) 80.1 ms.
+// misses), so here the product runs on its own with a 128 x 128 tile, half the
+// bytes per flop, at the cost of one FP64 write and two FP64 reads of V per
+// element (a few ms per batch).  Measured on the 80-core, 1200-virtual,
+// 4000-auxiliary workload, ms per batch of 512 pairs for both kernels: fused BF16
+// kernel (which this replaced) 62.6; with two LDS buffers 128 x 64 tiles (4 waves,
+// two workgroups per CU) 58.6, 128 x 128 tiles (8 waves, one per CU) 59.9,
+// 128 x 32 tiles 80.1; with three buffers, on one box, 128 x 64 53.1 and
+// 128 x 128 51.1: the second chunk in flight hides the load latency that one
+// workgroup per CU exposed at every barrier.
 //
-// Tile of the V kernel: 4 waves, wave (wr, wc) owns rows 64 wr .. 64 wr + 63
-// (two 32 x 32 MFMA blocks) and columns 32 wc .. 32 wc + 31; two workgroups per
-// CU.  Staging: 16-wide contraction chunks of a 128-row and a 64-row panel go
-// from global memory straight into LDS (global_load_lds, 16 bytes per lane, no
-// register round trip), triple buffered with two chunks in flight (72 KB of LDS,
-// still two workgroups per CU; 3% faster than double buffering); every wave moves
-// 6 of the 24 kilobytes of a chunk.  One LDS row holds the chunk of one virtual: 8 slots of 16 bytes
+// Tile of the V kernel: 8 waves, wave (wr, wc) owns rows 64 wr .. 64 wr + 63
+// (two 32 x 32 MFMA blocks) and columns 32 wc .. 32 wc + 31; one workgroup per
+// CU.  Staging: 16-wide contraction chunks of two 128-row panels go from global
+// memory straight into LDS (global_load_lds, 16 bytes per lane, no register
+// round trip), triple buffered with two chunks in flight (96 KB of LDS); every
+// wave moves 4 of the 32 kilobytes of a chunk.  One LDS row holds the chunk of
+// one virtual: 8 slots of 16 bytes
 // (slice t, half h -> slot 2t + h; slots >= 2 NS are padding), XOR-swizzled by
 // f(r) = (r ^ (r >> 3)) & 7 so that the fragment reads (eight or sixteen
 // consecutive rows, one logical slot) hit distinct banks and each direct load
@@ -69,7 +72,7 @@ namespace {
 constexpr int TV = 128;               // V tile edge
 constexpr int KC = 16;
 constexpr int SLOTS = 8;
-constexpr int kVWaveCols = 2;         // column waves: 128 x 64 tiles, 4 waves, two workgroups per CU
+constexpr int kVWaveCols = 4;         // column waves: 128 x 128 tiles, 8 waves, one workgroup per CU
 constexpr int FLUSH_CHUNKS = 128 / KC;
 typedef uint32_t u4 __attribute__((ext_vector_type(4)));
 typedef __attribute__((address_space(3))) void lds_void;
@@ -95,7 +98,6 @@ __global__ __launch_bounds__(128 * WC, 4 / WC) void pair_v_bf16_kernel(PairSlice
   __shared__ u4 lds0[(KB_A + KB_B) * 64];
   __shared__ u4 lds1[(KB_A + KB_B) * 64];
   __shared__ u4 lds2[(KB_A + KB_B) * 64];
-  static_assert(KB_W == 6, "the wait below counts one chunk's loads per wave");
   const int per_pair = nti * ntj;
   const int L = xcd_block_v(blockIdx.x, per_pair * a.n_blk_pairs);
   const int p = L / per_pair, t = L - p * per_pair;
@@ -178,12 +180,12 @@ __global__ __launch_bounds__(128 * WC, 4 / WC) void pair_v_bf16_kernel(PairSlice
   };
   // three buffers, two chunks in flight: chunk c + 2 streams in while chunk c is
   // multiplied out; the wait before the barrier lets the newest chunk's loads
-  // (6 per wave) stay outstanding, so only chunk c + 1 must have landed
+  // (KB_W per wave) stay outstanding, so only chunk c + 1 must have landed
   auto step = [&](int c, u4* cur, u4* nxt2) {
     const bool more = c + 2 < nchunk;
     if (more) load_chunk(c + 2, nxt2);
     compute(cur, c);
-    if (more) asm volatile("s_waitcnt vmcnt(6)" ::: "memory");
+    if (more) asm volatile("s_waitcnt vmcnt(%0)" ::"n"(KB_W) : "memory");
     else asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();
   };
@@ -191,7 +193,7 @@ __global__ __launch_bounds__(128 * WC, 4 / WC) void pair_v_bf16_kernel(PairSlice
   load_chunk(0, lds0);
   if (nchunk > 1) {
     load_chunk(1, lds1);
-    asm volatile("s_waitcnt vmcnt(6)" ::: "memory");
+    asm volatile("s_waitcnt vmcnt(%0)" ::"n"(KB_W) : "memory");
   } else {
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
   }
