@@ -57,10 +57,21 @@ __global__ __launch_bounds__(256) void split_t_bf16_kernel(const double* T, int 
   const int A = blockIdx.x / nt, C = blockIdx.x - (blockIdx.x / nt) * nt, q = blockIdx.y;
   const double* Tp = T + (size_t)q * n_v * n_v;
   const int tid = threadIdx.x;
-  for (int e = tid; e < TB * TB; e += 256) {
-    const int r = e >> 6, c = e & 63;
-    const int hr = C * TB + r, hc = A * TB + c;
-    tm[r][c] = (hr < n_v && hc < n_v) ? Tp[(size_t)hr * n_v + hc] : 0.0;
+  if (VEC) {  // 16-byte loads of column pairs (the vector-load data path is the limit)
+    for (int e = tid; e < TB * TB / 2; e += 256) {
+      const int r = e >> 5, c = 2 * (e & 31);
+      const int hr = C * TB + r, hc = A * TB + c;
+      const double2 v = (hr < n_v && hc < n_v) ? *reinterpret_cast<const double2*>(Tp + (size_t)hr * n_v + hc)
+                                               : make_double2(0.0, 0.0);
+      tm[r][c] = v.x;
+      tm[r][c + 1] = v.y;
+    }
+  } else {
+    for (int e = tid; e < TB * TB; e += 256) {
+      const int r = e >> 6, c = e & 63;
+      const int hr = C * TB + r, hc = A * TB + c;
+      tm[r][c] = (hr < n_v && hc < n_v) ? Tp[(size_t)hr * n_v + hc] : 0.0;
+    }
   }
   const int r = tid >> 2, k4 = tid & 3;
   const int row = A * TB + r;
