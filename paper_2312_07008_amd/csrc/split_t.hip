@@ -40,6 +40,51 @@ namespace {
 constexpr int TB = 64;
 constexpr int LD = TB + 1;
 typedef uint32_t u4 __attribute__((ext_vector_type(4)));
+
+// Amplitudes of workgroup (row block A, column block C) of pair matrix Tp: the
+// mirror tile tm[r][c] = T[C*64 + r][A*64 + c] (whole-row loads) and, for thread
+// (row r = tid / 4, quarter k4 = tid % 4), x[j] = T[A*64 + r][C*64 + 16 k4 + j];
+// zeros outside n_v.  VEC (n_v even): rows start 16-byte aligned and columns
+// come in pairs below n_v, so both are read with 16-byte loads (these kernels are
+// bound by the vector-load data path).  Ends with a barrier.
+template <bool VEC>
+__device__ inline void load_amplitudes(const double* Tp, int n_v, int A, int C, double (*tm)[LD], double* x) {
+  const int tid = threadIdx.x;
+  if (VEC) {
+    for (int e = tid; e < TB * TB / 2; e += 256) {
+      const int r = e >> 5, c = 2 * (e & 31);
+      const int hr = C * TB + r, hc = A * TB + c;
+      const double2 v = (hr < n_v && hc < n_v) ? *reinterpret_cast<const double2*>(Tp + (size_t)hr * n_v + hc)
+                                               : make_double2(0.0, 0.0);
+      tm[r][c] = v.x;
+      tm[r][c + 1] = v.y;
+    }
+  } else {
+    for (int e = tid; e < TB * TB; e += 256) {
+      const int r = e >> 6, c = e & 63;
+      const int hr = C * TB + r, hc = A * TB + c;
+      tm[r][c] = (hr < n_v && hc < n_v) ? Tp[(size_t)hr * n_v + hc] : 0.0;
+    }
+  }
+  const int row = A * TB + (tid >> 2), k4 = tid & 3;
+  if (VEC) {
+    const double2* src = reinterpret_cast<const double2*>(Tp + (size_t)row * n_v + C * TB + k4 * 16);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int gc = C * TB + k4 * 16 + 2 * j;
+      const double2 v = (row < n_v && gc < n_v) ? src[j] : make_double2(0.0, 0.0);
+      x[2 * j] = v.x;
+      x[2 * j + 1] = v.y;
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      const int gc = C * TB + k4 * 16 + j;
+      x[j] = (row < n_v && gc < n_v) ? Tp[(size_t)row * n_v + gc] : 0.0;
+    }
+  }
+  __syncthreads();
+}
 }  // namespace
 
 // ---------------------------------------------------------------- slices
@@ -57,42 +102,10 @@ __global__ __launch_bounds__(256) void split_t_bf16_kernel(const double* T, int 
   const int A = blockIdx.x / nt, C = blockIdx.x - (blockIdx.x / nt) * nt, q = blockIdx.y;
   const double* Tp = T + (size_t)q * n_v * n_v;
   const int tid = threadIdx.x;
-  if (VEC) {  // 16-byte loads of column pairs (the vector-load data path is the limit)
-    for (int e = tid; e < TB * TB / 2; e += 256) {
-      const int r = e >> 5, c = 2 * (e & 31);
-      const int hr = C * TB + r, hc = A * TB + c;
-      const double2 v = (hr < n_v && hc < n_v) ? *reinterpret_cast<const double2*>(Tp + (size_t)hr * n_v + hc)
-                                               : make_double2(0.0, 0.0);
-      tm[r][c] = v.x;
-      tm[r][c + 1] = v.y;
-    }
-  } else {
-    for (int e = tid; e < TB * TB; e += 256) {
-      const int r = e >> 6, c = e & 63;
-      const int hr = C * TB + r, hc = A * TB + c;
-      tm[r][c] = (hr < n_v && hc < n_v) ? Tp[(size_t)hr * n_v + hc] : 0.0;
-    }
-  }
   const int r = tid >> 2, k4 = tid & 3;
   const int row = A * TB + r;
   double x[16];
-  if (VEC) {  // n_v even: rows start 16-byte aligned and columns come in pairs below n_v
-    const double2* src = reinterpret_cast<const double2*>(Tp + (size_t)row * n_v + C * TB + k4 * 16);
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const int gc = C * TB + k4 * 16 + 2 * j;
-      const double2 v = (row < n_v && gc < n_v) ? src[j] : make_double2(0.0, 0.0);
-      x[2 * j] = v.x;
-      x[2 * j + 1] = v.y;
-    }
-  } else {
-#pragma unroll
-    for (int j = 0; j < 16; ++j) {
-      const int gc = C * TB + k4 * 16 + j;
-      x[j] = (row < n_v && gc < n_v) ? Tp[(size_t)row * n_v + gc] : 0.0;
-    }
-  }
-  __syncthreads();
+  load_amplitudes<VEC>(Tp, n_v, A, C, tm, x);
   double y[16];
 #pragma unroll
   for (int j = 0; j < 16; ++j) y[j] = tm[k4 * 16 + j][r];
@@ -134,27 +147,17 @@ __global__ __launch_bounds__(256) void split_t_bf16_kernel(const double* T, int 
 // [q][m][n_v_pad/32][n_v_pad][NS][32] bytes, and the row exponents E - 6 in
 // rexp[q][m][n_v_pad] (0 for zero rows).  Thread (row r, quarter k4) holds 16
 // consecutive columns, i.e. one half of a 32-wide chunk: one 16-byte store per digit.
-template <int NS>
+template <int NS, bool VEC>
 __global__ __launch_bounds__(256) void split_t_i8_kernel(const double* T, int n_v, int n_v_pad, int nt,
                                                          const unsigned long long* tmax, int8_t* out, int* rexp) {
   __shared__ double tm[TB][LD];  // T[C-block row][A-block col]
   const int A = blockIdx.x / nt, C = blockIdx.x - (blockIdx.x / nt) * nt, q = blockIdx.y;
   const double* Tp = T + (size_t)q * n_v * n_v;
   const int tid = threadIdx.x;
-  for (int e = tid; e < TB * TB; e += 256) {
-    const int r = e >> 6, c = e & 63;
-    const int hr = C * TB + r, hc = A * TB + c;
-    tm[r][c] = (hr < n_v && hc < n_v) ? Tp[(size_t)hr * n_v + hc] : 0.0;
-  }
   const int r = tid >> 2, k4 = tid & 3;
   const int row = A * TB + r;
   double x[16];
-#pragma unroll
-  for (int j = 0; j < 16; ++j) {
-    const int gc = C * TB + k4 * 16 + j;
-    x[j] = (row < n_v && gc < n_v) ? Tp[(size_t)row * n_v + gc] : 0.0;
-  }
-  __syncthreads();
+  load_amplitudes<VEC>(Tp, n_v, A, C, tm, x);
   double y[16];
 #pragma unroll
   for (int j = 0; j < 16; ++j) y[j] = tm[k4 * 16 + j][r];
@@ -260,13 +263,23 @@ hipError_t launch_split_t_i8(const double* T, const int2* pairs, const double* p
   const int nt = n_v_pad / TB;
   hipError_t e;
   dim3 grid(nt * nt, n_pairs), block(256);
+  const bool vec = (n_v % 2) == 0;
+#define SPLIT_T_I8(NS_)                                                                                         \
+  do {                                                                                                          \
+    if (vec)                                                                                                    \
+      hipLaunchKernelGGL((split_t_i8_kernel<NS_, true>), grid, block, 0, st, T, n_v, n_v_pad, nt, tmax, out, rexp); \
+    else                                                                                                        \
+      hipLaunchKernelGGL((split_t_i8_kernel<NS_, false>), grid, block, 0, st, T, n_v, n_v_pad, nt, tmax, out,    \
+                         rexp);                                                                                 \
+  } while (0)
   switch (ns) {
-    case 2: hipLaunchKernelGGL(split_t_i8_kernel<2>, grid, block, 0, st, T, n_v, n_v_pad, nt, tmax, out, rexp); break;
-    case 3: hipLaunchKernelGGL(split_t_i8_kernel<3>, grid, block, 0, st, T, n_v, n_v_pad, nt, tmax, out, rexp); break;
-    case 4: hipLaunchKernelGGL(split_t_i8_kernel<4>, grid, block, 0, st, T, n_v, n_v_pad, nt, tmax, out, rexp); break;
-    case 5: hipLaunchKernelGGL(split_t_i8_kernel<5>, grid, block, 0, st, T, n_v, n_v_pad, nt, tmax, out, rexp); break;
+    case 2: SPLIT_T_I8(2); break;
+    case 3: SPLIT_T_I8(3); break;
+    case 4: SPLIT_T_I8(4); break;
+    case 5: SPLIT_T_I8(5); break;
     default: return hipErrorInvalidValue;
   }
+#undef SPLIT_T_I8
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(diag_accumulate_kernel, dim3(n_v), dim3(256), 0, st, dgp, pairs, pw, w, n_pairs, nt, n_v_pad,
                      diag);
