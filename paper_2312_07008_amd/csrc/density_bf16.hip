@@ -29,8 +29,9 @@
 // there: the operand matrices are rows_pad rows apart, and those rows are never
 // written or used.  Staging as in pair_bf16_v.hip: 16-wide chunks of the 128-row
 // X panel and the 64-row Y panel go from global memory straight into LDS
-// (XOR-swizzled 128-byte rows), triple buffered with two chunks in flight, 24 KB
-// per buffer, two workgroups per CU.  The 1-D launch is
+// (XOR-swizzled 128-byte rows), double buffered, 24 KB per buffer, two
+// workgroups per CU; each step issues the next chunk's loads before its fragment
+// reads and waits for them before its closing barrier.  The 1-D launch is
 // remapped so that every XCD walks a contiguous range of (split, tile):
 // workgroups resident on one XCD read the same pairs' slices.
 #include "common.h"
@@ -76,8 +77,6 @@ __global__ __launch_bounds__(256, 2) void density_bf16_kernel(DensitySlicedArgs 
   static_assert(KB_W * 4 == KB_X + KB_Y, "whole kilobytes per wave");
   __shared__ u4 lds0[(KB_X + KB_Y) * 64];
   __shared__ u4 lds1[(KB_X + KB_Y) * 64];
-  __shared__ u4 lds2[(KB_X + KB_Y) * 64];
-  static_assert(KB_W == 6, "the wait below counts one chunk's loads per wave");
   const int L = xcd_block_d(blockIdx.x, a.nTP * a.nsplit);
   const int split = L / a.nTP, td = L - split * a.nTP;
   int I, J;
@@ -187,11 +186,11 @@ __global__ __launch_bounds__(256, 2) void density_bf16_kernel(DensitySlicedArgs 
   };
   int cp = p0, cch = 0, half = 0;  // pair, chunk and product of the step being computed
   double wp = (total > 0) ? weight(p0) : 0.0;
-  // three buffers, two chunks in flight (as in pair_bf16_v.hip): the wait before
-  // the barrier lets the newest chunk's 6 loads per wave stay outstanding
-  auto step = [&](int idx, u4* cur, u4* nxt2) {
-    const bool more = idx + 2 < total;
-    if (more) load_chunk(idx + 2, nxt2);
+  // step idx: the loads of step idx + 1 go out first and overlap the products of
+  // step idx; all have landed at the closing barrier (buffers swapped through
+  // pointers, as in pair_bf16_v.hip)
+  auto step = [&](int idx, u4* cur, u4* nxt) {
+    if (idx + 1 < total) load_chunk(idx + 1, nxt);
     compute(cur);
     const bool prod_end = (cch + 1 == ncc);
     flush(cch, prod_end, wp);
@@ -207,27 +206,20 @@ __global__ __launch_bounds__(256, 2) void density_bf16_kernel(DensitySlicedArgs 
     } else {
       ++cch;
     }
-    if (more) asm volatile("s_waitcnt vmcnt(6)" ::: "memory");
-    else asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();
   };
 
   if (total > 0) {
     load_chunk(0, lds0);
-    if (total > 1) {
-      load_chunk(1, lds1);
-      asm volatile("s_waitcnt vmcnt(6)" ::: "memory");
-    } else {
-      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-    }
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();
-    u4 *cur = lds0, *nx1 = lds1, *nx2 = lds2;  // steps idx, idx + 1, idx + 2
+    u4 *cur = lds0, *nxt = lds1;  // steps idx, idx + 1
     for (int idx = 0; idx < total; ++idx) {
-      step(idx, cur, nx2);
+      step(idx, cur, nxt);
       u4* t = cur;
-      cur = nx1;
-      nx1 = nx2;
-      nx2 = t;
+      cur = nxt;
+      nxt = t;
     }
   }
 

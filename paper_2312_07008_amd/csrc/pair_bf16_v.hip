@@ -38,19 +38,26 @@
 // bytes per flop, at the cost of one FP64 write and two FP64 reads of V per
 // element (a few ms per batch).  Measured on the 80-core, 1200-virtual,
 // 4000-auxiliary workload, ms per batch of 512 pairs for both kernels: fused BF16
-// kernel (which this replaced) 62.6; with two LDS buffers 128 x 64 tiles (4 waves,
-// two workgroups per CU) 58.6, 128 x 128 tiles (8 waves, one per CU) 59.9,
-// 128 x 32 tiles 80.1; with three buffers, on one box, 128 x 64 53.1 and
-// 128 x 128 51.1: the second chunk in flight hides the load latency that one
-// workgroup per CU exposed at every barrier.
+// kernel (which this replaced) 62.6; with the chunk loads placed late in each step
+// (two fixed LDS buffers, below the fragment reads where the compiler scheduled
+// them) 128 x 64 tiles (4 waves, two workgroups per CU) 58.6, 128 x 128 tiles
+// (8 waves, one per CU) 59.9, 128 x 32 tiles 80.1; with the loads first in the
+// step, on one box, 128 x 64 53.1 and 128 x 128 51.1.
 //
 // Tile of the V kernel: 8 waves, wave (wr, wc) owns rows 64 wr .. 64 wr + 63
 // (two 32 x 32 MFMA blocks) and columns 32 wc .. 32 wc + 31; one workgroup per
 // CU.  Staging: 16-wide contraction chunks of two 128-row panels go from global
 // memory straight into LDS (global_load_lds, 16 bytes per lane, no register
-// round trip), triple buffered with two chunks in flight (96 KB of LDS); every
-// wave moves 4 of the 32 kilobytes of a chunk.  One LDS row holds the chunk of
-// one virtual: 8 slots of 16 bytes
+// round trip), double buffered (64 KB of LDS); every wave moves 4 of the 32
+// kilobytes of a chunk.  Step c issues the loads of chunk c + 1 before its
+// fragment reads, so they overlap the products of chunk c, and waits for all of
+// them before the barrier that closes the step.  Measured on the same workload,
+// ms per batch, each against the kernel of the time on the same box: the newest
+// chunk's loads kept outstanding across a bare s_barrier (two chunks in flight)
+// 66.6 vs 50.9; the loads issued after the products 54.5 vs 50.9; two chunks per
+// barrier in 128 KB 50.4 vs 49.7; a ring of three buffers with the loads two
+// chunks ahead (also waited for at each barrier) 51.1-51.3, the same as this.
+// One LDS row holds the chunk of one virtual: 8 slots of 16 bytes
 // (slice t, half h -> slot 2t + h; slots >= 2 NS are padding), XOR-swizzled by
 // f(r) = (r ^ (r >> 3)) & 7 so that the fragment reads (eight or sixteen
 // consecutive rows, one logical slot) hit distinct banks and each direct load
@@ -97,7 +104,6 @@ __global__ __launch_bounds__(128 * WC, 4 / WC) void pair_v_bf16_kernel(PairSlice
   static_assert(KB_W * 2 * WC == KB_A + KB_B, "whole kilobytes per wave");
   __shared__ u4 lds0[(KB_A + KB_B) * 64];
   __shared__ u4 lds1[(KB_A + KB_B) * 64];
-  __shared__ u4 lds2[(KB_A + KB_B) * 64];
   const int per_pair = nti * ntj;
   const int L = xcd_block_v(blockIdx.x, per_pair * a.n_blk_pairs);
   const int p = L / per_pair, t = L - p * per_pair;
@@ -178,33 +184,26 @@ __global__ __launch_bounds__(128 * WC, 4 / WC) void pair_v_bf16_kernel(PairSlice
         }
     }
   };
-  // three buffers, two chunks in flight: chunk c + 2 streams in while chunk c is
-  // multiplied out; the wait before the barrier lets the newest chunk's loads
-  // (KB_W per wave) stay outstanding, so only chunk c + 1 must have landed
-  auto step = [&](int c, u4* cur, u4* nxt2) {
-    const bool more = c + 2 < nchunk;
-    if (more) load_chunk(c + 2, nxt2);
+  // step c: the loads of chunk c + 1 go out first, so they overlap the products
+  // of chunk c, and have all landed at the barrier that closes the step.  The
+  // buffers are swapped through pointers: over two fixed buffers in an unrolled
+  // loop the compiler moved the loads below the fragment reads.
+  auto step = [&](int c, u4* cur, u4* nxt) {
+    if (c + 1 < nchunk) load_chunk(c + 1, nxt);
     compute(cur, c);
-    if (more) asm volatile("s_waitcnt vmcnt(%0)" ::"n"(KB_W) : "memory");
-    else asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();
   };
 
   load_chunk(0, lds0);
-  if (nchunk > 1) {
-    load_chunk(1, lds1);
-    asm volatile("s_waitcnt vmcnt(%0)" ::"n"(KB_W) : "memory");
-  } else {
-    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-  }
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
   __syncthreads();
-  u4 *cur = lds0, *nx1 = lds1, *nx2 = lds2;  // chunks c, c + 1, c + 2
+  u4 *cur = lds0, *nxt = lds1;  // chunks c, c + 1
   for (int c = 0; c < nchunk; ++c) {
-    step(c, cur, nx2);
+    step(c, cur, nxt);
     u4* t = cur;
-    cur = nx1;
-    nx1 = nx2;
-    nx2 = t;
+    cur = nxt;
+    nxt = t;
   }
 
   // V^{ij}[ga][gb] in FP64 (register r of lane l: row 8(r/4) + 4(l/32) + r%4, column l%32)
