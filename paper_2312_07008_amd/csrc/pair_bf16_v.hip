@@ -107,7 +107,12 @@ __global__ __launch_bounds__(128 * WC, 4 / WC) void pair_v_bf16_kernel(PairSlice
   const int per_pair = nti * ntj;
   const int L = xcd_block_v(blockIdx.x, per_pair * a.n_blk_pairs);
   const int p = L / per_pair, t = L - p * per_pair;
-  const int I = t / ntj, J = t - (t / ntj) * ntj;
+  // tiles of one pair in bands of HB tile rows, taken column by column within a
+  // band: the ~32 workgroups resident on one XCD then read about 6 + 5 panels
+  // instead of the 14 of 3-4 whole tile rows (1% faster than row order)
+  constexpr int HB = 6;
+  const int band = t / (HB * ntj), h = min(HB, nti - band * HB), r = t - band * HB * ntj;
+  const int J = r / h, I = band * HB + (r - (r / h) * h);
   const int2 pr = a.pairs[p];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int wr = w / WC, wc = w - (w / WC) * WC;

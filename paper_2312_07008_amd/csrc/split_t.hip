@@ -41,6 +41,16 @@ constexpr int TB = 64;
 constexpr int LD = TB + 1;
 typedef uint32_t u4 __attribute__((ext_vector_type(4)));
 
+// value of the lane k ^ 1 (CTRL = 0xB1, quad_perm [1,0,3,2]) or k ^ 2 (0x4E,
+// [2,3,0,1]) of the lane's quad, by DPP moves of the two halves
+template <int CTRL>
+__device__ inline double quad_xor(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)b, CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xf, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 // Amplitudes of workgroup (row block A, column block C) of pair matrix Tp: the
 // mirror tile tm[r][c] = T[C*64 + r][A*64 + c] (whole-row loads) and, for thread
 // (row r = tid / 4, quarter k4 = tid % 4), x[j] = T[A*64 + r][C*64 + 16 k4 + j];
@@ -68,13 +78,39 @@ __device__ inline void load_amplitudes(const double* Tp, int n_v, int A, int C, 
   }
   const int row = A * TB + (tid >> 2), k4 = tid & 3;
   if (VEC) {
-    const double2* src = reinterpret_cast<const double2*>(Tp + (size_t)row * n_v + C * TB + k4 * 16);
+    // lane k4 of the row's quad reads 16-byte piece 4 j + k4 of the row's 64
+    // columns, so the quad reads 64 contiguous bytes per load; the quad then
+    // transposes the pieces (exchange rounds with partners k4 ^ 1 and k4 ^ 2) so
+    // that lane k4 holds pieces 8 k4 .. 8 k4 + 7, i.e. columns 16 k4 .. + 15
+    const double* src = Tp + (size_t)row * n_v + C * TB;
+    double2 pc[8];
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
-      const int gc = C * TB + k4 * 16 + 2 * j;
-      const double2 v = (row < n_v && gc < n_v) ? src[j] : make_double2(0.0, 0.0);
-      x[2 * j] = v.x;
-      x[2 * j + 1] = v.y;
+      const int c0 = 2 * (4 * j + k4);
+      pc[j] = (row < n_v && C * TB + c0 < n_v) ? *reinterpret_cast<const double2*>(src + c0) : make_double2(0.0, 0.0);
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      double2 m[4] = {pc[h], pc[2 + h], pc[4 + h], pc[6 + h]};  // lane k4: pieces 8 t + 4 h + k4
+#pragma unroll
+      for (int k = 1; k <= 2; k <<= 1) {
+        const bool hi = (k4 & k) != 0;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          if (t & k) continue;
+          const double2 snd = hi ? m[t] : m[t | k];
+          double2 rcv;
+          rcv.x = k == 1 ? quad_xor<0xB1>(snd.x) : quad_xor<0x4E>(snd.x);
+          rcv.y = k == 1 ? quad_xor<0xB1>(snd.y) : quad_xor<0x4E>(snd.y);
+          if (hi) m[t] = rcv;
+          else m[t | k] = rcv;
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {  // now piece 8 k4 + 4 h + t
+        x[2 * (4 * h + t)] = m[t].x;
+        x[2 * (4 * h + t) + 1] = m[t].y;
+      }
     }
   } else {
 #pragma unroll
@@ -90,7 +126,8 @@ __device__ inline void load_amplitudes(const double* Tp, int n_v, int A, int C, 
 // ---------------------------------------------------------------- slices
 // Workgroup = (row block A, column block C, pair q): rows A x columns C of the
 // four matrices.  x = T[a][c] comes straight from global memory (thread = row,
-// 16-column quarter: 128 contiguous bytes, 16-byte loads when n_v is even),
+// 16-column quarter; when n_v is even, 16-byte loads in which the four threads
+// of a row read 64 contiguous bytes, then a transpose within the four),
 // y = T[c][a] from the mirror tile T[C, A] staged in LDS.  The thread's 16
 // columns are exactly one 16-wide chunk of the output row, so its slices of each
 // matrix (32 NS contiguous bytes) are stored straight from registers; the four
