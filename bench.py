@@ -267,8 +267,8 @@ def main():
                          "kernel of known traffic for hardware-counter runs)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported (the pass would "
-              "shard hole pairs over GPUs with one D_vv all-reduce, which is not built here)", file=sys.stderr)
+        print(f"bench.py: measures one GPU; --gpus {args.gpus} is not supported (the pass would shard hole "
+              "pairs over GPUs with one D_vv all-reduce, which is not implemented)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

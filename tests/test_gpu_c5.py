@@ -7,7 +7,7 @@ mixed path (1e-6 Eh).  The correction E_full - E_kept depends on the natural
 orbitals, which two FP64 eigensolvers (the library's and LAPACK in the oracle) give
 only to rounding: at |E_kept| ~ 7e7 Eh that alone moves E_kept by ~1e-16 |E_kept|
 per orbital rotation, so the FP64 bound on the correction is max(1e-8, 2e-15
-|E_kept|) Eh (1.3e-7 Eh here).  About a minute on the GPU machine, most of it drawing
+|E_kept|) Eh (1.3e-7 Eh here).  About a minute on an MI355X, most of it drawing
 the 12.7 GB of inputs."""
 import json
 import os
