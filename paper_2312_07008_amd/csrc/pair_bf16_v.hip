@@ -114,6 +114,9 @@ __global__ __launch_bounds__(128 * WC, 4 / WC) void pair_v_bf16_kernel(PairSlice
   const int band = t / (HB * ntj), h = min(HB, nti - band * HB), r = t - band * HB * ntj;
   const int J = r / h, I = band * HB + (r - (r / h) * h);
   const int2 pr = a.pairs[p];
+  // V^{ii} is symmetric and its epilogue takes Q from P: the tiles wholly below
+  // the diagonal are never read (the whole workgroup leaves before any barrier)
+  if (pr.x == pr.y && I * TV >= (J + 1) * TJ) return;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int wr = w / WC, wc = w - (w / WC) * WC;
 
@@ -241,6 +244,7 @@ __global__ __launch_bounds__(256) void pair_epi_bf16_kernel(PairSlicedArgs a) {
   const int n_v = a.n_v;
   const double* Vp = a.T + (size_t)p * n_v * n_v;
   const int gb = J * 64 + wc * 32 + r32;
+  const bool same = pr.x == pr.y;
   double dP[16], dQ[16];
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
@@ -249,7 +253,9 @@ __global__ __launch_bounds__(256) void pair_epi_bf16_kernel(PairSlicedArgs a) {
     dP[r] = ok ? Vp[(size_t)ga * n_v + gb] : 0.0;  // V^{ij}_{ab}
     dQ[r] = ok ? Vp[(size_t)gb * n_v + ga] : 0.0;  // V^{ji}_{ab} = V^{ij}_{ba}
   }
-  if (pr.x == pr.y) {
+  // i == j: V^{ii} is symmetric and the product kernel leaves its tiles below the
+  // diagonal unwritten, so Q is P (the values just read there are discarded)
+  if (same) {
 #pragma unroll
     for (int r = 0; r < 16; ++r) dQ[r] = dP[r];
   }
