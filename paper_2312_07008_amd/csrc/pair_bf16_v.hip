@@ -250,14 +250,11 @@ __global__ __launch_bounds__(256) void pair_epi_bf16_kernel(PairSlicedArgs a) {
   for (int r = 0; r < 16; ++r) {
     const int ga = I * 64 + wr * 32 + 8 * (r >> 2) + 4 * hq + (r & 3);
     const bool ok = ga < n_v && gb < n_v;
-    dP[r] = ok ? Vp[(size_t)ga * n_v + gb] : 0.0;  // V^{ij}_{ab}
-    dQ[r] = ok ? Vp[(size_t)gb * n_v + ga] : 0.0;  // V^{ji}_{ab} = V^{ij}_{ba}
-  }
-  // i == j: V^{ii} is symmetric and the product kernel leaves its tiles below the
-  // diagonal unwritten, so Q is P (the values just read there are discarded)
-  if (same) {
-#pragma unroll
-    for (int r = 0; r < 16; ++r) dQ[r] = dP[r];
+    // V^{ji}_{ab} = V^{ij}_{ba}; for i == j, V^{ii} is symmetric and the product
+    // kernel leaves its tiles below the diagonal unwritten, so Q is read where P is
+    const size_t pa = (size_t)ga * n_v + gb, qa = same ? pa : (size_t)gb * n_v + ga;
+    dP[r] = ok ? Vp[pa] : 0.0;  // V^{ij}_{ab}
+    dQ[r] = ok ? Vp[qa] : 0.0;
   }
   __syncthreads();  // every read of this tile pair's V precedes the T written over it
   sliced_pair_epilogue<STORE>(a, p, tp, I, J, pr.x, pr.y, dP, dQ, scratch);
