@@ -290,6 +290,56 @@ def test_recanonicalized_fock_is_diagonal():
     np.testing.assert_allclose(U.T @ U, np.eye(6), atol=1e-13)
 
 
+def _random_orthogonal(n, seed):
+    q, r = np.linalg.qr(np.random.default_rng(seed).standard_normal((n, n)))
+    return q * np.sign(np.diag(r))[None, :]
+
+
+def _energy_without_recanonicalization(inp, no_kept, s):
+    """A wrong kept-space energy for the checks below: B transformed by the kept NOs
+    as they are, denominators from the diagonal of F' = V_k^T diag(eps_v) V_k."""
+    F = no_kept.T @ (inp.eps_vir[:, None] * no_kept)
+    Bt = o.transform_b(inp.B, no_kept)
+    return o.pt2_pass(inp.eps_core, inp.eps_act, np.diag(F).copy(), inp.gamma_act, Bt, s, False).energy
+
+
+@pytest.mark.parametrize("n_act", [0, 2])
+def test_kept_energy_depends_only_on_the_kept_space(n_act):
+    """Sec. 2 rebuilds the Hamiltonian in the span of the kept NOs and
+    recanonicalizes it, so E_kept is a function of that subspace alone: any
+    rotation R of the kept NO columns leaves it unchanged.  Skipping the
+    recanonicalization (or using diag F') breaks this, and the check shows it."""
+    inp = synth.generate(3, n_act, 12, 10, seed=23)
+    s, k = 0.5, 7
+    occ, vecs = o.natural_orbitals(o.pt2_pass_inputs(inp, s).D_vv)
+    R = _random_orthogonal(k, 5)
+    e0 = o.kept_energy(inp, vecs, k, s)
+    e1 = o.kept_energy(inp, vecs[:, :k] @ R, k, s)
+    scale = abs(e0[0])
+    assert o.dd_sub(e0, e1)[0] == pytest.approx(0.0, abs=1e-13 * scale)
+    w0 = _energy_without_recanonicalization(inp, vecs[:, :k], s)
+    w1 = _energy_without_recanonicalization(inp, vecs[:, :k] @ R, s)
+    assert abs(o.dd_sub(w0, w1)[0]) > 1e-6 * scale
+
+
+@pytest.mark.parametrize("n_act,seed", [(0, 29), (2, 31)])
+def test_kept_energy_on_canonical_virtual_subset(n_act, seed):
+    """When the kept space is spanned by a subset S of the canonical virtuals, the
+    recanonicalized basis is that subset (the eps_a are distinct), so E_kept must
+    equal the plain pass on the sub-problem (eps_v[S], B[:, S, :]) -- whatever
+    rotation within span(S) the kept vectors arrive in."""
+    inp = synth.generate(3, n_act, 11, 9, seed=seed)
+    s = 0.7
+    S = np.sort(np.random.default_rng(seed).choice(inp.n_vir, size=6, replace=False))
+    no_kept = np.eye(inp.n_vir)[:, S] @ _random_orthogonal(len(S), seed + 1)
+    e_kept = o.kept_energy(inp, no_kept, len(S), s)
+    sub = o.pt2_pass(inp.eps_core, inp.eps_act, inp.eps_vir[S], inp.gamma_act,
+                     np.ascontiguousarray(inp.B[:, S, :]), s, False).energy
+    assert abs(o.dd_sub(e_kept, sub)[0]) <= 1e-13 * abs(sub[0])
+    wrong = _energy_without_recanonicalization(inp, no_kept, s)
+    assert abs(o.dd_sub(wrong, sub)[0]) > 1e-6 * abs(sub[0])
+
+
 # ---------------------------------------------------------------------------
 # The reading of the input recipe, checked against independently computed values
 # ---------------------------------------------------------------------------
