@@ -48,15 +48,24 @@
 // (two 32 x 32 MFMA blocks) and columns 32 wc .. 32 wc + 31; one workgroup per
 // CU.  Staging: 16-wide contraction chunks of two 128-row panels go from global
 // memory straight into LDS (global_load_lds, 16 bytes per lane, no register
-// round trip), double buffered (64 KB of LDS); every wave moves 4 of the 32
-// kilobytes of a chunk.  Step c issues the loads of chunk c + 1 before its
-// fragment reads, so they overlap the products of chunk c, and waits for all of
-// them before the barrier that closes the step.  Measured on the same workload,
-// ms per batch, each against the kernel of the time on the same box: the newest
-// chunk's loads kept outstanding across a bare s_barrier (two chunks in flight)
-// 66.6 vs 50.9; the loads issued after the products 54.5 vs 50.9; two chunks per
-// barrier in 128 KB 50.4 vs 49.7; a ring of three buffers with the loads two
-// chunks ahead (also waited for at each barrier) 51.1-51.3, the same as this.
+// round trip) through a ring of four 32 KB slots; every wave moves 4 of the 32
+// kilobytes of a chunk.  Step c issues the loads of chunk c + 3, runs the
+// products of chunk c, waits for its own loads of chunk c + 1 only and closes
+// with a barrier that carries no memory fence, so two chunks stay in flight
+// across it.  (The fence of __syncthreads waits for every outstanding load; the
+// ring slots are distinct LDS arrays so that the compiler's alias scopes keep it
+// from waiting for all loads before a fragment read.)  Same results bit for bit
+// as the two-buffer form with one chunk in flight, and 1% faster (53.8 -> 53.1 ms
+// per batch of 512 pairs at 1200 virtuals and 4000 auxiliary functions).
+// Measured on that workload, ms per batch, with variants compiled from this
+// kernel: the same products with constant fragments instead of the LDS reads
+// 39.6, only the chunk loads and barriers (no products, no reads) 32.5, ring of
+// three 54.0, s_setprio raised around the products 53.9, 128 x 64 tiles with two
+// workgroups per CU 53.3, slabs stored chunk-major (each step reads two
+// contiguous 16 KB blocks) 53.7.  The direct loads deliver about 21 bytes per
+// clock per CU, so the loads alone take 60% of the kernel, and the fragment reads
+// of all eight waves, issued together after each barrier, cost another 14 ms
+// that the products do not hide.
 // One LDS row holds the chunk of one virtual: 8 slots of 16 bytes
 // (slice t, half h -> slot 2t + h; slots >= 2 NS are padding), XOR-swizzled by
 // f(r) = (r ^ (r >> 3)) & 7 so that the fragment reads (eight or sixteen
@@ -69,6 +78,8 @@
 // so that every XCD walks a contiguous range of (pair, tile) in order: the
 // workgroups resident on one XCD then belong to one or two pairs and share the
 // same slabs B_i, B_j through that XCD's L2.
+#include <type_traits>
+
 #include "common.h"
 #include "kernels.h"
 #include "pair_epilogue.h"
@@ -80,6 +91,7 @@ constexpr int TV = 128;               // V tile edge
 constexpr int KC = 16;
 constexpr int SLOTS = 8;
 constexpr int kVWaveCols = 4;         // column waves: 128 x 128 tiles, 8 waves, one workgroup per CU
+constexpr int kVRing = 4;             // LDS ring slots: loads run three chunks ahead
 constexpr int FLUSH_CHUNKS = 128 / KC;
 typedef uint32_t u4 __attribute__((ext_vector_type(4)));
 typedef __attribute__((address_space(3))) void lds_void;
@@ -93,17 +105,42 @@ __device__ inline int xcd_block_v(int h, int nblk) {
 }
 }  // namespace
 
+// s_waitcnt immediate (gfx9 encoding) that waits until at most n vector-memory
+// operations of this wave are outstanding and leaves the other counters alone.
+// Issued through the builtin, not inline asm, so that the compiler's own wait
+// insertion sees it and does not add a vmcnt(0) before the LDS reads.
+constexpr int vm_wait_imm(int n) { return (n & 15) | (((n >> 4) & 3) << 14) | (7 << 4) | (15 << 8); }
+
 // WC column waves: tile 128 x (32 WC) of V, 2 WC waves, wave (wr, wc) owns rows
-// 64 wr .. + 63 and columns 32 wc .. + 31
-template <int NS, int WC>
+// 64 wr .. + 63 and columns 32 wc .. + 31.  NBUF LDS buffers form a ring: the
+// loads run NBUF - 1 chunks ahead of the products.
+template <int NS, int WC, int NBUF>
 __global__ __launch_bounds__(128 * WC, 4 / WC) void pair_v_bf16_kernel(PairSlicedArgs a, int nti, int ntj) {
   static_assert(2 * NS <= SLOTS, "slices per LDS row");
+  static_assert(NBUF >= 2 && NBUF <= 4, "ring of 2 to 4 buffers");
   constexpr int TJ = 32 * WC;                     // V tile columns
   constexpr int KB_A = TV / 8, KB_B = TJ / 8;     // kilobytes of the two panels per chunk
   constexpr int KB_W = (KB_A + KB_B) / (2 * WC);  // kilobytes per wave per chunk
   static_assert(KB_W * 2 * WC == KB_A + KB_B, "whole kilobytes per wave");
-  __shared__ u4 lds0[(KB_A + KB_B) * 64];
-  __shared__ u4 lds1[(KB_A + KB_B) * 64];
+  // distinct arrays per ring slot and panel: the compiler's alias scopes then
+  // tell the slots apart, so a read of one slot does not wait for the loads into
+  // another; the panel-A slots (and the panel-B slots) lie within the 64 KB reach
+  // of one ds_read offset, so one address register serves a fragment in every slot
+  __shared__ u4 la0[KB_A * 64], la1[KB_A * 64], la2[NBUF > 2 ? KB_A * 64 : 1], la3[NBUF > 3 ? KB_A * 64 : 1];
+  __shared__ u4 lb0[KB_B * 64], lb1[KB_B * 64], lb2[NBUF > 2 ? KB_B * 64 : 1], lb3[NBUF > 3 ? KB_B * 64 : 1];
+  // ring slot K as a compile-time index (no pointer to a slot is ever stored)
+  auto slot_a = [&](auto K) -> u4* {
+    if constexpr (K() == 0) return la0;
+    else if constexpr (K() == 1) return la1;
+    else if constexpr (K() == 2) return la2;
+    else return la3;
+  };
+  auto slot_b = [&](auto K) -> u4* {
+    if constexpr (K() == 0) return lb0;
+    else if constexpr (K() == 1) return lb1;
+    else if constexpr (K() == 2) return lb2;
+    else return lb3;
+  };
   const int per_pair = nti * ntj;
   const int L = xcd_block_v(blockIdx.x, per_pair * a.n_blk_pairs);
   const int p = L / per_pair, t = L - p * per_pair;
@@ -134,13 +171,18 @@ __global__ __launch_bounds__(128 * WC, 4 / WC) void pair_v_bf16_kernel(PairSlice
     const int ts = sl >> 1, h = sl & 1;
     return (uint32_t)(row * row_bytes + (ts < NS ? ts * 32 + h * 16 : 0));
   };
-  auto load_chunk = [&](int chunk, u4* buf) {
+  const int nchunk = a.n_aux_pad / KC;
+  auto load_chunk = [&](int chunk, auto K) {  // chunk < nchunk; into slot K
     const size_t coff = (size_t)chunk * (KC * NS * 2);
 #pragma unroll
     for (int m = 0; m < KB_W; ++m) {
       const int kb = KB_W * q_w + m;  // wave-uniform
-      const char* src = kb < KB_A ? panelA + coff + src_off(kb) : panelB + coff + src_off(kb - KB_A);
-      __builtin_amdgcn_global_load_lds((gbl_void*)src, (lds_void*)(buf + kb * 64), 16, 0, 0);
+      if (kb < KB_A)
+        __builtin_amdgcn_global_load_lds((gbl_void*)(panelA + coff + src_off(kb)), (lds_void*)(slot_a(K) + kb * 64), 16,
+                                         0, 0);
+      else
+        __builtin_amdgcn_global_load_lds((gbl_void*)(panelB + coff + src_off(kb - KB_A)),
+                                         (lds_void*)(slot_b(K) + (kb - KB_A) * 64), 16, 0, 0);
     }
   };
 
@@ -156,23 +198,38 @@ __global__ __launch_bounds__(128 * WC, 4 / WC) void pair_v_bf16_kernel(PairSlice
     for (int r = 0; r < 16; ++r) dV[b][r] = 0.0;
   }
 
-  const int nchunk = a.n_aux_pad / KC;
   const int r32 = lane & 31, hq = lane >> 5;
-  const int rowB = wc * 32 + r32, fB = swz_v(rowB);
-  constexpr int PB = KB_A * 64;  // u4 offset of panel B in a buffer
-
-  auto compute = [&](const u4* buf, int c) {
-    bf8v fb[NS];
+  // per-lane u4 index of every fragment within a slot (row, swizzled logical slot);
+  // passed through an empty asm in every step, so that the compiler forms each
+  // slot's addresses at the read instead of holding NBUF x 3 NS of them in registers
+  int offB[NS], offA[2][NS];
+  {
+    const int rowB = wc * 32 + r32, fB = swz_v(rowB);
 #pragma unroll
-    for (int s = 0; s < NS; ++s)
-      fb[s] = __builtin_bit_cast(bf8v, buf[PB + rowB * SLOTS + ((2 * s + hq) ^ fB)]);
+    for (int s = 0; s < NS; ++s) offB[s] = rowB * SLOTS + ((2 * s + hq) ^ fB);
 #pragma unroll
     for (int b = 0; b < 2; ++b) {
       const int rowA = wr * 64 + b * 32 + r32, fA = swz_v(rowA);
+#pragma unroll
+      for (int s = 0; s < NS; ++s) offA[b][s] = rowA * SLOTS + ((2 * s + hq) ^ fA);
+    }
+  }
+
+  auto compute = [&](auto K, int c) {  // chunk c from slot K
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      asm volatile("" : "+v"(offB[s]));
+      asm volatile("" : "+v"(offA[0][s]));
+      asm volatile("" : "+v"(offA[1][s]));
+    }
+    bf8v fb[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) fb[s] = __builtin_bit_cast(bf8v, slot_b(K)[offB[s]]);
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
       bf8v fa[NS];
 #pragma unroll
-      for (int s = 0; s < NS; ++s)
-        fa[s] = __builtin_bit_cast(bf8v, buf[rowA * SLOTS + ((2 * s + hq) ^ fA)]);
+      for (int s = 0; s < NS; ++s) fa[s] = __builtin_bit_cast(bf8v, slot_a(K)[offA[b][s]]);
 #pragma unroll
       for (int s = 0; s < NS; ++s)
 #pragma unroll
@@ -192,27 +249,74 @@ __global__ __launch_bounds__(128 * WC, 4 / WC) void pair_v_bf16_kernel(PairSlice
         }
     }
   };
-  // step c: the loads of chunk c + 1 go out first, so they overlap the products
-  // of chunk c, and have all landed at the barrier that closes the step.  The
-  // buffers are swapped through pointers: over two fixed buffers in an unrolled
-  // loop the compiler moved the loads below the fragment reads.
-  auto step = [&](int c, u4* cur, u4* nxt) {
-    if (c + 1 < nchunk) load_chunk(c + 1, nxt);
+  // the workgroup barrier without the memory fence of __syncthreads (whose
+  // release waits for every outstanding load, vmcnt(0)); the empty asm keeps the
+  // compiler from moving memory accesses across it
+  auto barrier = [] {
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+  };
+  // step c: the loads of chunk c + NBUF - 1 go into the slot chunk c - 1 was read
+  // from (every wave finished those reads before the last barrier), the products
+  // of chunk c follow, then each wave waits for its own loads of chunk c + 1 --
+  // the KB_W (NBUF - 2) loads issued after them may stay in flight -- and the
+  // barrier makes every wave's part of chunk c + 1 visible.  The steady-state loop
+  // has no branch around a load or a wait (a merge of paths with different
+  // outstanding loads makes the compiler wait for all of them); the last
+  // 2 NBUF - 2 or fewer steps run in a tail that checks each load and waits for
+  // everything.
+  auto step = [&](int c, auto cur, auto nxt) {
+    load_chunk(c + NBUF - 1, nxt);
     compute(cur, c);
-    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-    __syncthreads();
+    __builtin_amdgcn_s_waitcnt(vm_wait_imm(KB_W * (NBUF - 2)));
+    barrier();
+  };
+  auto tail_step = [&](int c, auto cur, auto nxt) {
+    if (c >= nchunk) return;  // uniform
+    if (c + NBUF - 1 < nchunk) load_chunk(c + NBUF - 1, nxt);
+    compute(cur, c);
+    __builtin_amdgcn_s_waitcnt(vm_wait_imm(0));
+    barrier();
+  };
+  using S0 = std::integral_constant<int, 0>;
+  using S1 = std::integral_constant<int, 1>;
+  using S2 = std::integral_constant<int, 2>;
+  using S3 = std::integral_constant<int, 3>;
+  auto ring = [&](int c, auto&& f) {
+    if constexpr (NBUF == 2) {
+      f(c, S0{}, S1{});
+      f(c + 1, S1{}, S0{});
+    } else if constexpr (NBUF == 3) {
+      f(c, S0{}, S2{});
+      f(c + 1, S1{}, S0{});
+      f(c + 2, S2{}, S1{});
+    } else {
+      f(c, S0{}, S3{});
+      f(c + 1, S1{}, S0{});
+      f(c + 2, S2{}, S1{});
+      f(c + 3, S3{}, S2{});
+    }
   };
 
-  load_chunk(0, lds0);
-  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-  __syncthreads();
-  u4 *cur = lds0, *nxt = lds1;  // chunks c, c + 1
-  for (int c = 0; c < nchunk; ++c) {
-    step(c, cur, nxt);
-    u4* t = cur;
-    cur = nxt;
-    nxt = t;
+  // chunks 0 .. NBUF - 2 before the first step (chunk k lives in slot k % NBUF)
+  if (nchunk >= 2 * NBUF - 1) {
+    load_chunk(0, S0{});
+    if constexpr (NBUF > 2) load_chunk(1, S1{});
+    if constexpr (NBUF > 3) load_chunk(2, S2{});
+    __builtin_amdgcn_s_waitcnt(vm_wait_imm(KB_W * (NBUF - 2)));  // chunk 0 has landed
+  } else {
+    if (nchunk > 0) load_chunk(0, S0{});
+    if (NBUF > 2 && nchunk > 1) load_chunk(1, S1{});
+    if (NBUF > 3 && nchunk > 2) load_chunk(2, S2{});
+    __builtin_amdgcn_s_waitcnt(vm_wait_imm(0));
   }
+  barrier();
+  int c = 0;
+  // steady state: every step of a revolution loads a chunk that exists
+  for (; c + 2 * NBUF - 2 < nchunk; c += NBUF) ring(c, step);
+  ring(c, tail_step);
+  if (c + NBUF < nchunk) ring(c + NBUF, tail_step);
 
   // V^{ij}[ga][gb] in FP64 (register r of lane l: row 8(r/4) + 4(l/32) + r%4, column l%32)
   const int n_v = a.n_v;
@@ -270,9 +374,9 @@ hipError_t launch_pair_v_bf16(const PairSlicedArgs& a, int ns, int n_pairs, hipS
   b.n_blk_pairs = n_pairs;
   dim3 gv(nti * ntj * n_pairs), bv(128 * WC);
   switch (ns) {
-    case 2: hipLaunchKernelGGL((pair_v_bf16_kernel<2, WC>), gv, bv, 0, st, b, nti, ntj); break;
-    case 3: hipLaunchKernelGGL((pair_v_bf16_kernel<3, WC>), gv, bv, 0, st, b, nti, ntj); break;
-    case 4: hipLaunchKernelGGL((pair_v_bf16_kernel<4, WC>), gv, bv, 0, st, b, nti, ntj); break;
+    case 2: hipLaunchKernelGGL((pair_v_bf16_kernel<2, WC, kVRing>), gv, bv, 0, st, b, nti, ntj); break;
+    case 3: hipLaunchKernelGGL((pair_v_bf16_kernel<3, WC, kVRing>), gv, bv, 0, st, b, nti, ntj); break;
+    case 4: hipLaunchKernelGGL((pair_v_bf16_kernel<4, WC, kVRing>), gv, bv, 0, st, b, nti, ntj); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
