@@ -234,6 +234,83 @@ def ladder_bench(args, wl, cfg):
     print(json.dumps(res), flush=True)
 
 
+def screen_gain(W, margin, s, p_o, prec, steps=3):
+    """What the learned screen gains on the localized variant of the headline sizes
+    (80 core holes, 1200 virtuals, 4000 auxiliary functions; hole and auxiliary
+    positions with xi = 1.25, so pair norms span many decades): the screened pass
+    (features, network, mask, then the pass on the surviving pairs) against the
+    unscreened pass at the same precision, both timed with inputs in HBM, judged by
+    the unscreened pass and by the plain FP64 pass on the same inputs."""
+    import numpy as np
+    import torch
+    import synth
+    import paper_2312_07008_amd as dp
+    from paper_2312_07008_amd import screening
+
+    t0 = time.time()
+    inp = synth.generate(80, 0, 1200, 4000, 0, label="c4loc", localized_xi=1.25)
+    d = dp.upload_inputs(inp)
+    del inp
+    log(f"screen gain: c4loc inputs in {time.time() - t0:.1f} s")
+    stream = torch.cuda.current_stream()
+    n_core, n_v = 80, 1200
+    n_up = n_core * (n_core + 1) // 2
+    opts = dp.make_opts(80, 0, 1200, 4000, s, precision=prec)
+    o64 = dp.make_opts(80, 0, 1200, 4000, s, precision=dp.FP64)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    r64 = dp.build_vv_density(o64, d["eps_hole"], d["eps_vir"], d["gamma_act"], d["B"], want_pair_tnorm=True,
+                              stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    fp64_ms = e0.elapsed_time(e1)
+    t64 = dp.fno_truncate(r64["D_vv"], p_o)
+    E64 = tuple(float(x) for x in r64["e_pt2"].cpu().numpy())
+    occ64, tn64 = t64["occ"].cpu().numpy(), r64["pair_tnorm"].cpu().numpy()
+    del r64
+    torch.cuda.empty_cache()
+    ws = torch.empty(dp.workspace_size(opts), dtype=torch.uint8, device="cuda")
+    D = torch.empty((n_v, n_v), dtype=torch.float64, device="cuda")
+    e = torch.empty(2, dtype=torch.float64, device="cuda")
+    out = {}
+    for name in ("unscreened", "screened"):
+        times, nd, mask = [], 0, None
+        for it in range(steps + 1):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            if name == "screened":
+                mask, nd = screening.predict_mask(W, opts, d["eps_hole"], d["eps_vir"], d["B"], SCREEN_THRESHOLD,
+                                                  margin, stream=stream)
+            dp.build_vv_density(opts, d["eps_hole"], d["eps_vir"], d["gamma_act"], d["B"], mask, D_vv=D, e_pt2=e,
+                                workspace=ws, stream=stream)
+            b.record(stream)
+            torch.cuda.synchronize()
+            if it:
+                times.append(a.elapsed_time(b))
+        t = dp.fno_truncate(D, p_o)
+        out[name] = dict(ms=statistics.median(times), E=tuple(float(x) for x in e.cpu().numpy()),
+                         occ=t["occ"].cpu().numpy(), n_kept=t["n_kept"], nd=nd,
+                         mask=None if mask is None else mask.cpu().numpy())
+        log(f"screen gain: {name} {out[name]['ms']:.1f} ms per pass, kept {t['n_kept']}, dropped {nd}")
+    del ws, D
+    torch.cuda.empty_cache()
+    u, sc = out["unscreened"], out["screened"]
+    mk = sc["mask"]
+    dropped = [(i, j) for i in range(n_core) for j in range(i, n_core) if mk[i, j] == 0]
+    wrong = sum(1 for i, j in dropped if not tn64[i, j] < SCREEN_THRESHOLD)
+    return {"workload": "c4loc: 80 core holes, 1200 virtuals, 4000 auxiliary functions, localized holes and "
+                        "auxiliary functions (xi = 1.25), seed 0",
+            "threshold": SCREEN_THRESHOLD, "pairs_total": n_up, "pairs_dropped": sc["nd"],
+            "pairs_dropped_above_threshold_in_fp64_pass": wrong,
+            "ms_per_pass_unscreened": u["ms"], "ms_per_pass_screened": sc["ms"],
+            "speedup_screened_vs_unscreened": u["ms"] / sc["ms"], "fp64_ms_per_pass": fp64_ms,
+            "speedup_screened_vs_fp64": fp64_ms / sc["ms"],
+            "delta_E_vs_unscreened_Eh": dd(sc["E"], u["E"]), "delta_E_vs_fp64_Eh": dd(sc["E"], E64),
+            "max_dON_vs_unscreened": float(np.abs(sc["occ"] - u["occ"]).max()),
+            "max_dON_vs_fp64": float(np.abs(sc["occ"] - occ64).max()),
+            "n_kept": {"screened": sc["n_kept"], "unscreened": u["n_kept"], "fp64": t64["n_kept"]}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -251,6 +328,9 @@ def main():
     ap.add_argument("--naf-scan", action="store_true",
                     help="after the timed steps: natural auxiliary functions at several relative thresholds, "
                          "the compression time, n_naf, and the pass time and energy on the compressed integrals")
+    ap.add_argument("--no-screen-gain", action="store_true",
+                    help="skip the screened-vs-unscreened measurement on the localized workload (c4loc) that a "
+                         "default c4 run reports in screen_gain")
     ap.add_argument("--no-alt", action="store_true",
                     help="skip the INT8-digit measurement reported beside a BF16 run")
     ap.add_argument("--ladder", action="store_true",
@@ -344,9 +424,14 @@ def main():
         log(f"calibration copy of {nbytes} bytes done")
         del src, dst
 
+    # the kept-space energy of the correction: INT8 digits after a BF16 or FP8 build (its
+    # exact integer sums hold the correction to 1e-6 Eh at the largest sizes, where the
+    # BF16 kept-space pass alone is off by ~2e-6 Eh), else the build's own precision
+    corr_prec = dp.INT8_SLICED if args.precision in ("bf16", "fp8") else prec
+    opts_corr = dp.make_opts(n_core, n_act, n_v, n_aux, s, precision=corr_prec)
     ws_pass = torch.empty(dp.workspace_size(opts), dtype=torch.uint8, device="cuda")
     ws_fno = torch.empty(dp.fno_truncate_workspace_size(n_v), dtype=torch.uint8, device="cuda")
-    ws_corr = torch.empty(dp.pt2_correction_workspace_size(opts, n_v), dtype=torch.uint8, device="cuda")
+    ws_corr = torch.empty(dp.pt2_correction_workspace_size(opts_corr, n_v), dtype=torch.uint8, device="cuda")
     D = torch.empty((n_v, n_v), dtype=torch.float64, device="cuda")
     e = torch.empty(2, dtype=torch.float64, device="cuda")
 
@@ -363,7 +448,7 @@ def main():
         ev[2].record(stream)
         tr = dp.fno_truncate(D, p_o, workspace=ws_fno, stream=stream)
         ev[3].record(stream)
-        c = dp.pt2_energy_correction(opts, d["eps_hole"], d["eps_vir"], d["gamma_act"], d["B"], tr["no_vecs"],
+        c = dp.pt2_energy_correction(opts_corr, d["eps_hole"], d["eps_vir"], d["gamma_act"], d["B"], tr["no_vecs"],
                                      tr["n_kept"], e, workspace=ws_corr, stream=stream)
         ev[4].record(stream)
         return ev, tr, c, nd
@@ -428,6 +513,8 @@ def main():
            "config": {"workload": f"{args.workload}: DF-DSRG-PT2 virtual-NO pass, {wl['gen'] or 'plain'} inputs",
                       "n_core": n_core, "n_act": n_act, "n_vir": n_v, "n_aux": n_aux, "s": s, "p_o": p_o,
                       "precision": args.precision, "slices": ns1, "screening": screen,
+                      "correction_precision": {dp.FP64: "fp64", dp.BF16_SLICED: "bf16", dp.FP8_SLICED: "fp8",
+                                               dp.INT8_SLICED: "int8"}[corr_prec],
                       "screen_threshold": SCREEN_THRESHOLD if screen else None},
            "ms_per_pass": ms_pass,
            "stage_ms_per_step": {"screen": screen_ms, "build": build_ms, "fno_truncate": fno_ms,
@@ -502,6 +589,10 @@ def main():
         log(f"INT8 digits: {out['alt_int8']['ms_per_pass']:.1f} ms per pass, kept {t8['n_kept']}")
         del ws8, D8
         torch.cuda.empty_cache()
+    if screen and args.workload == "c4" and not args.no_screen_gain:
+        del ws_pass, ws_fno, ws_corr
+        torch.cuda.empty_cache()
+        out["screen_gain"] = screen_gain(W, margin, s, p_o, prec)
     if ref is not None:
         out["fp64_ms_per_pass"] = ref["ms"]
         out["speedup_vs_fp64"] = ref["ms"] / ms_pass

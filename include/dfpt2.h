@@ -61,7 +61,12 @@ typedef enum {
 typedef enum {
   DFPT2_FP64 = 0,         /* FP64 MFMA for both contractions */
   DFPT2_BF16_SLICED = 1,  /* B and T split into BF16 slices; exact FP32 chunk sums, FP64 across chunks */
-  DFPT2_FP8_SLICED = 2,   /* FP8 e4m3 slices with per-block power-of-two scales */
+  DFPT2_FP8_SLICED = 2,   /* FP8 e4m3 slices with per-block power-of-two scales.  Measured and
+                             offered beside the others, but OUTSIDE the 1e-6 Eh energy contract of
+                             the mixed paths: products of differently scaled 32-element blocks meet
+                             in one FP32 accumulator, so the sums are not exact; the relative energy
+                             error is about 1e-8 .. 3e-7 at 4 slices (bounded by 8 x 2^-(5 slices - 1)),
+                             i.e. up to ~1e-2 Eh on the 1e6 - 1e8 Eh energies of large inputs */
   DFPT2_INT8_SLICED = 3   /* B and T as balanced base-256 INT8 digits per row; exact INT32 level sums on
                              the INT8 MFMA (n_aux <= 26208 at 5 digits) */
 } dfpt2_precision;
@@ -256,7 +261,10 @@ int pt2_correction_workspace_size(const dfpt2_opts* opts, int64_t n_kept, size_t
  *   e_kept      [2] out, E_PT2 in the recanonicalized kept basis
  *   correction  [2] out, e_full - e_kept
  * The kept space is recanonicalized: F' = V_k^T diag(eps_vir) V_k = W diag(eps~) W^T,
- * U = V_k W, B~_i = U^T B_i, and the pass is repeated with (eps~, B~).
+ * U = V_k W, B~_i = U^T B_i, and the pass is repeated with (eps~, B~) in the arithmetic
+ * opts->precision names.  It need not be the build's: after a BF16 build, INT8 digits
+ * (exact integer sums) hold the correction within 1e-6 Eh up to 120 + 12 holes, 2000
+ * virtuals and 6000 auxiliary functions, where a BF16 kept-space pass is off by ~2e-6 Eh.
  * Errors: INVALID_ARG, WORKSPACE, HIP, NOT_CONVERGED, NONFINITE, UNSUPPORTED.
  */
 int pt2_energy_correction(const dfpt2_opts* opts, const double* eps_hole, const double* eps_vir,
@@ -325,8 +333,10 @@ int pairscreen_build_mask(const float* pred, const double* log_scale, int64_t n_
  * Stage timers for measurement (not part of the method).  When enabled, every
  * entry point brackets its kernel launches with HIP events on the stream it was
  * given and, at its next stream synchronization, adds the elapsed GPU time to
- * the stage counters below.  Counters are process-global; enable and read them
- * from one host thread.  dfpt2_profile_enable(1) also resets them.
+ * the stage counters below.  Counters, and the enabled flag, are per host thread
+ * (thread-local): a thread enables and reads its own, and only the calls it makes
+ * are timed, so the library keeps no state shared between threads.
+ * dfpt2_profile_enable(1) also resets the calling thread's counters.
  *   ms        host out [DFPT2_NSTAGE], accumulated milliseconds per stage
  *   launches  host out [DFPT2_NSTAGE], number of timed launches per stage
  */

@@ -154,15 +154,7 @@ int plan_pass(const dfpt2_opts* o, PassPlan* pl, bool energy_only) {
                                                       : 0);
   p.off_norm2 = take(p.precision != DFPT2_FP64 ? sizeof(double) * (size_t)p.n_h * p.n_v : 0);
   p.off_rexp = take(p.precision == DFPT2_INT8_SLICED ? sizeof(int) * (size_t)p.n_h * p.n_v_pad : 0);
-  // density operands: BF16 slices, or INT8 digits (+ row exponents) with INT8 precision
-  const size_t t_bytes = p.precision == DFPT2_INT8_SLICED ? 1 : sizeof(__bf16);
-  p.off_Ts = take(p.ns2 >= 2 ? t_bytes * 4 * (size_t)p.batch * p.n_v_rows_t * p.n_v_pad_d * p.ns2 : 0);
-  p.off_Texp = take(p.ns2 >= 2 && p.precision == DFPT2_INT8_SLICED ? sizeof(int) * 4 * (size_t)p.batch * p.n_v_pad_d
-                                                                    : 0);
-  p.off_dg = take(p.ns2 >= 2 ? sizeof(double) * (size_t)p.batch * (p.n_v_pad_d / 64) * p.n_v_pad_d : 0);
-  p.off_tmax = take(p.ns2 >= 2 ? sizeof(unsigned long long) * 4 * (size_t)p.batch * p.n_v_pad_d : 0);
-  p.off_diag = take(p.ns2 >= 2 ? sizeof(double) * (size_t)p.n_v : 0);
-  // active holes: stacked amplitude/integral matrices before and after the rotation
+  // active holes: core batches of the core-active block (cpb cores x n_act pairs each)
   p.n_ca = p.n_core * p.n_act;
   p.n_aa_un = p.n_act * (p.n_act + 1) / 2;
   if (p.n_act > 0) {
@@ -173,6 +165,23 @@ int plan_pass(const dfpt2_opts* o, PassPlan* pl, bool energy_only) {
     if (cpb > p.n_core) cpb = p.n_core > 0 ? p.n_core : 1;
     p.cpb = cpb;
     p.act_cap = p.n_act * p.n_act > p.n_act * cpb ? p.n_act * p.n_act : p.n_act * cpb;
+  }
+  // density operands: BF16 slices, or INT8 digits (+ row exponents) with INT8 precision,
+  // for a batch of core pairs or of the active blocks' rotated amplitudes
+  int nb_t = p.batch;
+  if (p.n_act > 0 && !energy_only) {
+    const int act_np = p.n_act * p.cpb > p.n_aa_un ? p.n_act * p.cpb : p.n_aa_un;
+    if (act_np > nb_t) nb_t = act_np;
+  }
+  const size_t t_bytes = p.precision == DFPT2_INT8_SLICED ? 1 : sizeof(__bf16);
+  p.off_Ts = take(p.ns2 >= 2 ? t_bytes * 4 * (size_t)nb_t * p.n_v_rows_t * p.n_v_pad_d * p.ns2 : 0);
+  p.off_Texp = take(p.ns2 >= 2 && p.precision == DFPT2_INT8_SLICED ? sizeof(int) * 4 * (size_t)nb_t * p.n_v_pad_d
+                                                                    : 0);
+  p.off_dg = take(p.ns2 >= 2 ? sizeof(double) * (size_t)nb_t * (p.n_v_pad_d / 64) * p.n_v_pad_d : 0);
+  p.off_tmax = take(p.ns2 >= 2 ? sizeof(unsigned long long) * 4 * (size_t)nb_t * p.n_v_pad_d : 0);
+  p.off_diag = take(p.ns2 >= 2 ? sizeof(double) * (size_t)p.n_v : 0);
+  // active holes: stacked amplitude/integral matrices before and after the rotation
+  if (p.n_act > 0) {
     const size_t ac = (size_t)p.act_cap;
     p.off_act_T = take(sizeof(double) * mat * ac);
     p.off_act_V = take(sizeof(double) * mat * ac);
@@ -301,6 +310,76 @@ hipError_t launch_pair(const PairLaunch& L, const PairKernelArgs& a, int n_pairs
   return hipErrorInvalidValue;  // BF16 needs amplitudes to store or a V buffer
 }
 
+// Density of amplitude matrices already in memory (matrix p at T + slot[p] n_v^2)
+// with per-pair weights pw, on the pass's sliced path: row data (maxima and
+// diagonal partials), operand slices (BF16) or digits (INT8), then the sliced
+// density product accumulated into Dpart and the exact diagonal into diag.
+static int sliced_density(const PassPlan& pl, const double* T, const int* slot, const int2* pairs, const double* pw,
+                          int np, double* Dpart, char* ws, hipStream_t s) {
+  hipError_t e;
+  auto* tmax = reinterpret_cast<unsigned long long*>(ws + pl.off_tmax);
+  double* dgp = reinterpret_cast<double*>(ws + pl.off_dg);
+  double* diag = reinterpret_cast<double*>(ws + pl.off_diag);
+  {
+    ProfScope ps(DFPT2_STAGE_SPLIT_T, s);
+    if ((e = launch_fill(reinterpret_cast<double*>(tmax), (size_t)np * 4 * pl.n_v_pad_d, 0.0, s)) != hipSuccess)
+      return hip_fail(e, "fill");
+    if ((e = launch_pair_row_stats(T, slot, np, pl.n_v, pl.n_v_pad_d, tmax, dgp, s)) != hipSuccess)
+      return hip_fail(e, "amplitude row data");
+  }
+  if (pl.precision == DFPT2_INT8_SLICED) {
+    int8_t* Ts = reinterpret_cast<int8_t*>(ws + pl.off_Ts);
+    int* Texp = reinterpret_cast<int*>(ws + pl.off_Texp);
+    {
+      ProfScope ps(DFPT2_STAGE_SPLIT_T, s);
+      if ((e = launch_split_t_i8(T, slot, pairs, pw, 1.0, np, pl.n_v, pl.n_v_pad_d, pl.ns2, tmax, dgp, Ts, Texp, diag,
+                                 s)) != hipSuccess)
+        return hip_fail(e, "amplitude digits");
+    }
+    DensityDigitArgs dd{};
+    dd.Ts = Ts;
+    dd.rexp = Texp;
+    dd.pw = pw;
+    dd.pairs = pairs;
+    dd.Dpart = Dpart;
+    dd.n_v = pl.n_v;
+    dd.n_v_pad = pl.n_v_pad_d;
+    dd.nt = pl.nt;
+    dd.nTP = pl.nTP;
+    dd.n_pairs = np;
+    dd.nsplit = pl.nsplit2 < np ? pl.nsplit2 : np;
+    dd.w = 1.0;
+    dd.accumulate = 1;
+    ProfScope ps(DFPT2_STAGE_DENSITY, s);
+    if ((e = launch_density_i8(dd, pl.ns2, s)) != hipSuccess) return hip_fail(e, "density kernel (INT8)");
+    return DFPT2_OK;
+  }
+  __bf16* Ts = reinterpret_cast<__bf16*>(ws + pl.off_Ts);
+  {
+    ProfScope ps(DFPT2_STAGE_SPLIT_T, s);
+    if ((e = launch_split_t_bf16(T, slot, pairs, pw, 1.0, np, pl.n_v, pl.n_v_pad_d, pl.n_v_rows_t, pl.ns2, tmax, dgp,
+                                 Ts, diag, s)) != hipSuccess)
+      return hip_fail(e, "amplitude split");
+  }
+  DensitySlicedArgs ds{};
+  ds.Ts = Ts;
+  ds.pw = pw;
+  ds.pairs = pairs;
+  ds.Dpart = Dpart;
+  ds.n_v = pl.n_v;
+  ds.n_v_pad = pl.n_v_pad_d;
+  ds.nt = pl.nt;
+  ds.nTP = pl.nTD;
+  ds.rows_pad = pl.n_v_rows_t;
+  ds.n_pairs = np;
+  ds.nsplit = pl.nsplit2 < np ? pl.nsplit2 : np;
+  ds.w = 1.0;
+  ds.accumulate = 1;
+  ProfScope ps(DFPT2_STAGE_DENSITY, s);
+  if ((e = launch_density_bf16(ds, pl.ns2, s)) != hipSuccess) return hip_fail(e, "density kernel (BF16)");
+  return DFPT2_OK;
+}
+
 // Active blocks of the pass (row a6): core-active pairs in batches of cores, then
 // the active-active block; amplitudes and renormalized integrals are rotated to
 // the natural basis of Gamma_act and fed to the density kernel with weights.
@@ -386,6 +465,10 @@ static int run_active_blocks(const PassPlan& pl, const dfpt2_opts& o, const doub
     if ((e = launch_weighted_pair_reduce(epart, ntile, np, we, pe_act + 2 * (size_t)m0 * na, s)) != hipSuccess)
       return hip_fail(e, "weighted reduce");
     if (pl.energy_only) continue;
+    if (pl.ns2 >= 2) {  // the pass's sliced density path, with the weights n_k
+      if ((st = sliced_density(pl, Tout, slots, pairs, wd, np, Dpart, ws, s)) != DFPT2_OK) return st;
+      continue;
+    }
     da.pairs = pairs;
     da.slot = slots;
     da.n_pairs = np;
@@ -418,7 +501,9 @@ static int run_active_blocks(const PassPlan& pl, const dfpt2_opts& o, const doub
       return hip_fail(e, "rotated energy");
     if ((e = launch_weighted_pair_reduce(epart, ntile, nu, we, pe_act + 2 * (size_t)pl.n_ca, s)) != hipSuccess)
       return hip_fail(e, "weighted reduce");
-    if (!pl.energy_only) {
+    if (!pl.energy_only && pl.ns2 >= 2) {
+      if ((st = sliced_density(pl, Tout, slots2, pairs2, wd, nu, Dpart, ws, s)) != DFPT2_OK) return st;
+    } else if (!pl.energy_only) {
       da.pairs = pairs2;
       da.slot = slots2;
       da.n_pairs = nu;
@@ -445,6 +530,9 @@ int run_pass(const PassPlan& pl, const dfpt2_opts& o, const double* eps_h, const
 
   PairLaunch L{pl.precision, pl.ns1, B, nullptr, nullptr, nullptr, pl.n_v_pad, pl.n_aux_pad, nullptr};
   if (pl.energy_only && pl.precision == DFPT2_BF16_SLICED) L.vbuf = reinterpret_cast<double*>(ws + pl.off_T);
+  // d_count[0]: pairs of the mask; d_count[1]: set by the BF16 split when a row of B
+  // lies below the range its slices need (both read back with one copy below)
+  if ((e = launch_fill(reinterpret_cast<double*>(d_count), 2, 0.0, s)) != hipSuccess) return hip_fail(e, "fill");
   if (pl.precision != DFPT2_FP64) {
     ProfScope ps(DFPT2_STAGE_SPLIT, s);
     double* nrm = reinterpret_cast<double*>(ws + pl.off_norm2);
@@ -452,7 +540,7 @@ int run_pass(const PassPlan& pl, const dfpt2_opts& o, const double* eps_h, const
     L.Bs = ws + pl.off_Bs;
     if (pl.precision == DFPT2_BF16_SLICED) {
       if ((e = launch_split_rows_bf16(B, pl.n_aux, pl.n_h, pl.n_v, pl.n_v_pad, pl.n_aux, pl.n_aux_pad, pl.ns1,
-                                      reinterpret_cast<__bf16*>(ws + pl.off_Bs), nrm, s)) != hipSuccess)
+                                      reinterpret_cast<__bf16*>(ws + pl.off_Bs), nrm, d_count + 1, s)) != hipSuccess)
         return hip_fail(e, "split");
     } else if (pl.precision == DFPT2_INT8_SLICED) {
       int* rexp = reinterpret_cast<int*>(ws + pl.off_rexp);
@@ -473,10 +561,16 @@ int run_pass(const PassPlan& pl, const dfpt2_opts& o, const double* eps_h, const
     if ((e = launch_build_pairs(mask, pl.n_core, pl.n_h, pairs, d_count, s)) != hipSuccess)
       return hip_fail(e, "build_pairs");
   }
-  int count = 0;
-  if ((e = hipMemcpyAsync(&count, d_count, sizeof(int), hipMemcpyDeviceToHost, s)) != hipSuccess)
+  int cnt[2] = {0, 0};
+  if ((e = hipMemcpyAsync(cnt, d_count, sizeof(cnt), hipMemcpyDeviceToHost, s)) != hipSuccess)
     return hip_fail(e, "count copy");
   if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "stream sync");
+  const int count = cnt[0];
+  if (cnt[1] != 0)
+    return fail(DFPT2_ERR_UNSUPPORTED,
+                "BF16 slicing: a row of B has max |B^Q_ia| below 2^%d, where products of its %d slices leave the "
+                "normal FP32 range; rescale the integrals or use FP64 or INT8 digits",
+                bf16_min_row_exponent(pl.ns1) - 1, pl.ns1);
 
   if (pair_energy) {
     // core-core entries start at 0 (masked pairs stay 0); pairs with an active hole are NaN
@@ -541,7 +635,7 @@ int run_pass(const PassPlan& pl, const dfpt2_opts& o, const double* eps_h, const
       int* Texp = reinterpret_cast<int*>(ws + pl.off_Texp);
       {
         ProfScope ps(DFPT2_STAGE_SPLIT_T, s);
-        if ((e = launch_split_t_i8(T, pairs + p0, nullptr, pl.w_density, np, pl.n_v, pl.n_v_pad_d, pl.ns2, pa.tmax,
+        if ((e = launch_split_t_i8(T, nullptr, pairs + p0, nullptr, pl.w_density, np, pl.n_v, pl.n_v_pad_d, pl.ns2, pa.tmax,
                                    pa.dgp, Ts, Texp, reinterpret_cast<double*>(ws + pl.off_diag), s)) != hipSuccess)
           return hip_fail(e, "amplitude digits");
       }
@@ -567,7 +661,7 @@ int run_pass(const PassPlan& pl, const dfpt2_opts& o, const double* eps_h, const
       __bf16* Ts = reinterpret_cast<__bf16*>(ws + pl.off_Ts);
       {
         ProfScope ps(DFPT2_STAGE_SPLIT_T, s);
-        if ((e = launch_split_t_bf16(T, pairs + p0, nullptr, pl.w_density, np, pl.n_v, pl.n_v_pad_d, pl.n_v_rows_t,
+        if ((e = launch_split_t_bf16(T, nullptr, pairs + p0, nullptr, pl.w_density, np, pl.n_v, pl.n_v_pad_d, pl.n_v_rows_t,
                                      pl.ns2, pa.tmax, pa.dgp, Ts, reinterpret_cast<double*>(ws + pl.off_diag), s)) !=
             hipSuccess)
           return hip_fail(e, "amplitude split");

@@ -55,9 +55,12 @@ hipError_t launch_pair_gemm_fp8(const PairSlicedArgs& a, int ns, int n_pairs, hi
 hipError_t launch_pair_gemm_i8(const PairSlicedArgs& a, int ns, int n_pairs, hipStream_t st);
 // largest n_aux_pad for which the INT8 level sums stay exact with ns digits
 int pair_i8_max_aux_pad(int ns);
-// FP64 rows -> BF16 / FP8 slices, see split.hip
+// FP64 rows -> BF16 / FP8 slices, see split.hip.  BF16: rows whose largest
+// magnitude lies below 2^(bf16_min_row_exponent(ns) - 1) set *range_flag (if non-null)
+__host__ __device__ constexpr int bf16_min_row_exponent(int ns) { return 8 - (126 - 9 * (ns - 1)) / 2; }
 hipError_t launch_split_rows_bf16(const double* X, long long ldx, int nb, int rows, int rows_pad, int ncols,
-                                  int ncols_pad, int ns, __bf16* out, double* norm2, hipStream_t st);
+                                  int ncols_pad, int ns, __bf16* out, double* norm2, int* range_flag,
+                                  hipStream_t st);
 hipError_t launch_split_rows_fp8(const double* X, long long ldx, int nb, int rows, int rows_pad, int ncols,
                                  int ncols_pad, int ns, uint8_t* out, uint32_t* scales, double* norm2,
                                  hipStream_t st);
@@ -96,9 +99,16 @@ int density_bf16_tiles(int nt);
 // kernel's partial sums dgp ([n_pairs][n_v_pad/64][n_v_pad]); the operand matrices
 // are rows_pad rows apart (a multiple of 64, >= n_v_pad); rows n_v .. n_v_pad - 1
 // are written as zeros, rows n_v_pad .. rows_pad - 1 are not written
-hipError_t launch_split_t_bf16(const double* T, const int2* pairs, const double* pw, double w, int n_pairs, int n_v,
-                               int n_v_pad, int rows_pad, int ns, const unsigned long long* tmax, const double* dgp,
-                               __bf16* out, double* diag, hipStream_t st);
+// (slot: matrix q is T + slot[q] n_v^2, or T + q n_v^2 when slot is null)
+hipError_t launch_split_t_bf16(const double* T, const int* slot, const int2* pairs, const double* pw, double w,
+                               int n_pairs, int n_v, int n_v_pad, int rows_pad, int ns,
+                               const unsigned long long* tmax, const double* dgp, __bf16* out, double* diag,
+                               hipStream_t st);
+// row maxima of the four density operands (tmax, atomic max: zero it first) and the
+// diagonal partials (dgp) of amplitude matrices T + slot[q] n_v^2 that did not come
+// out of a pair-kernel epilogue
+hipError_t launch_pair_row_stats(const double* T, const int* slot, int n_pairs, int n_v, int n_v_pad,
+                                 unsigned long long* tmax, double* dgp, hipStream_t st);
 hipError_t launch_density_bf16(const DensitySlicedArgs& a, int ns, hipStream_t st);
 
 // INT8-digit density: digits of the four operands (split_t.hip) and the digit product
@@ -112,9 +122,9 @@ struct DensityDigitArgs {
   double w;             // weight of one ordered pair
   int accumulate;
 };
-hipError_t launch_split_t_i8(const double* T, const int2* pairs, const double* pw, double w, int n_pairs, int n_v,
-                             int n_v_pad, int ns, const unsigned long long* tmax, const double* dgp, int8_t* out,
-                             int* rexp, double* diag, hipStream_t st);
+hipError_t launch_split_t_i8(const double* T, const int* slot, const int2* pairs, const double* pw, double w,
+                             int n_pairs, int n_v, int n_v_pad, int ns, const unsigned long long* tmax,
+                             const double* dgp, int8_t* out, int* rexp, double* diag, hipStream_t st);
 hipError_t launch_density_i8(const DensityDigitArgs& a, int ns, hipStream_t st);
 // D = sum of the split slices (+ diag on the diagonal if non-null), both triangles
 hipError_t launch_density_reduce(const double* Dpart, int nsplit, int n_v, const double* diag, double* D,

@@ -21,7 +21,9 @@ struct Profiler {
   std::vector<Pending> pending;
   std::vector<hipEvent_t> pool;
 };
-Profiler g_prof;
+// one set of counters per host thread: a pass is timed by the thread that issues it,
+// and threads that run passes concurrently do not see each other's stages
+thread_local Profiler g_prof;
 
 hipEvent_t get_event() {
   if (!g_prof.pool.empty()) {

@@ -6,11 +6,16 @@
 //     s_t = rint(r_{t-1} 2^9), r_t = r_{t-1} 2^9 - s_t   (|s_t| <= 256)
 //     slice_t = s_t 2^(E - 8 - 9 (t-1))                    (exact in BF16: 8-bit integers
 //                                                          times a power of two)
-// so x = sum_t slice_t + O(2^(E - 8 - 9 k)).  (Rows whose largest magnitude is
-// below 2^-90 would push trailing slices into BF16's subnormal range and lose
-// bits.)  Every slice of a row is an integer multiple of that row's unit 2^(E - 8 - 9(t-1)); products of slices from two
+// so x = sum_t slice_t + O(2^(E - 8 - 9 k)).  Every slice of a row is an integer
+// multiple of that row's unit 2^(E - 8 - 9(t-1)); products of slices from two
 // rows are integer multiples of one common unit, which is what makes the FP32
 // MFMA sums of the leading levels exact (see pair_bf16_v.hip).
+// Range: the deepest kept level of two rows with exponent E is a multiple of
+// 2^(2(E - 8) - 9(k - 1)), which must stay a normal FP32 number (>= 2^-126) for
+// the sums to keep their bits; rows with 0 < max|x| < 2^(E_min - 1),
+// E_min = bf16_min_row_exponent(k), set *range_flag and the pass reports the
+// input as unsupported for BF16 slicing (FP64 and INT8 digits have no such
+// limit).  E_min is -41 at k = 4, i.e. rows below ~2e-13.
 // Slices are written true-scale, so a dot product of slices needs no rescaling.
 //
 // The kernel also returns every row's squared norm in FP64.  The pair kernel uses
@@ -31,7 +36,7 @@ namespace dfpt2 {
 // blockIdx.y is the matrix index.  norm2 [nb][rows] gets the squared row norms.
 __global__ __launch_bounds__(256) void split_rows_bf16_kernel(const double* X, long long ldx, int rows,
                                                               int rows_pad, int ncols, int ncols_pad, int ns,
-                                                              __bf16* out, double* norm2) {
+                                                              __bf16* out, double* norm2, int* range_flag) {
   const int lane = threadIdx.x & 63;
   const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
   const int b = blockIdx.y, nb = gridDim.y;
@@ -56,6 +61,7 @@ __global__ __launch_bounds__(256) void split_rows_bf16_kernel(const double* X, l
   if (norm2 && lane == 0) norm2[(size_t)b * rows + row] = q;
   int E = 0;
   if (m > 0.0) frexp(m, &E);
+  if (range_flag && lane == 0 && m > 0.0 && E < bf16_min_row_exponent(ns)) atomicOr(range_flag, 1);
   for (int c = lane; c < ncols_pad; c += 64) {
     double r = (c < ncols && m > 0.0) ? ldexp(x[c], -E) * 256.0 : 0.0;
     int sh = E - 8;
@@ -69,10 +75,11 @@ __global__ __launch_bounds__(256) void split_rows_bf16_kernel(const double* X, l
 }
 
 hipError_t launch_split_rows_bf16(const double* X, long long ldx, int nb, int rows, int rows_pad, int ncols,
-                                  int ncols_pad, int ns, __bf16* out, double* norm2, hipStream_t st) {
+                                  int ncols_pad, int ns, __bf16* out, double* norm2, int* range_flag,
+                                  hipStream_t st) {
   if (rows_pad <= 0 || nb <= 0) return hipSuccess;
   hipLaunchKernelGGL(split_rows_bf16_kernel, dim3((rows_pad + 3) / 4, nb), dim3(256), 0, st, X, ldx, rows,
-                     rows_pad, ncols, ncols_pad, ns, out, norm2);
+                     rows_pad, ncols, ncols_pad, ns, out, norm2, range_flag);
   return hipGetLastError();
 }
 

@@ -133,11 +133,12 @@ __device__ inline void load_amplitudes(const double* Tp, int n_v, int A, int C, 
 // matrix (32 NS contiguous bytes) are stored straight from registers; the four
 // threads of a row write 128 NS contiguous bytes.
 template <int NS, bool VEC>
-__global__ __launch_bounds__(256) void split_t_bf16_kernel(const double* T, int n_v, int n_v_pad, int rows_pad,
-                                                           int nt, const unsigned long long* tmax, __bf16* out) {
+__global__ __launch_bounds__(256) void split_t_bf16_kernel(const double* T, const int* slot, int n_v, int n_v_pad,
+                                                           int rows_pad, int nt, const unsigned long long* tmax,
+                                                           __bf16* out) {
   __shared__ double tm[TB][LD];  // T[C-block row][A-block col]
   const int A = blockIdx.x / nt, C = blockIdx.x - (blockIdx.x / nt) * nt, q = blockIdx.y;
-  const double* Tp = T + (size_t)q * n_v * n_v;
+  const double* Tp = T + (size_t)(slot ? slot[q] : q) * n_v * n_v;
   const int tid = threadIdx.x;
   const int r = tid >> 2, k4 = tid & 3;
   const int row = A * TB + r;
@@ -185,11 +186,12 @@ __global__ __launch_bounds__(256) void split_t_bf16_kernel(const double* T, int 
 // rexp[q][m][n_v_pad] (0 for zero rows).  Thread (row r, quarter k4) holds 16
 // consecutive columns, i.e. one half of a 32-wide chunk: one 16-byte store per digit.
 template <int NS, bool VEC>
-__global__ __launch_bounds__(256) void split_t_i8_kernel(const double* T, int n_v, int n_v_pad, int nt,
-                                                         const unsigned long long* tmax, int8_t* out, int* rexp) {
+__global__ __launch_bounds__(256) void split_t_i8_kernel(const double* T, const int* slot, int n_v, int n_v_pad,
+                                                         int nt, const unsigned long long* tmax, int8_t* out,
+                                                         int* rexp) {
   __shared__ double tm[TB][LD];  // T[C-block row][A-block col]
   const int A = blockIdx.x / nt, C = blockIdx.x - (blockIdx.x / nt) * nt, q = blockIdx.y;
-  const double* Tp = T + (size_t)q * n_v * n_v;
+  const double* Tp = T + (size_t)(slot ? slot[q] : q) * n_v * n_v;
   const int tid = threadIdx.x;
   const int r = tid >> 2, k4 = tid & 3;
   const int row = A * TB + r;
@@ -237,6 +239,64 @@ __global__ __launch_bounds__(256) void split_t_i8_kernel(const double* T, int n_
   }
 }
 
+// ---------------------------------------------------------------- row data
+// The row data the split kernels read, for amplitude matrices that did not pass
+// through a pair-kernel epilogue (the amplitudes of the active blocks, rotated to
+// the natural orbitals of Gamma_act): for matrix T = T + slot[q] n_v^2, the
+// largest magnitudes of the rows of T, T^T, 2T - T^T and 2T^T - T (atomic max on
+// the bit patterns of non-negative doubles, so independent of order) and the
+// diagonal partial sums 2 (x^2 - x y + y^2) per (row a, 64-column block C), as
+// pair_epilogue.h records them.  Workgroup (A, C, q) as in the split kernels.
+template <bool VEC>
+__global__ __launch_bounds__(256) void pair_row_stats_kernel(const double* T, const int* slot, int n_v, int n_v_pad,
+                                                             int nt, unsigned long long* tmax, double* dgp) {
+  __shared__ double tm[TB][LD];
+  const int A = blockIdx.x / nt, C = blockIdx.x - (blockIdx.x / nt) * nt, q = blockIdx.y;
+  const double* Tp = T + (size_t)(slot ? slot[q] : q) * n_v * n_v;
+  const int tid = threadIdx.x;
+  const int r = tid >> 2, k4 = tid & 3;
+  const int row = A * TB + r;
+  double x[16];
+  load_amplitudes<VEC>(Tp, n_v, A, C, tm, x);
+  double mx[4] = {0.0, 0.0, 0.0, 0.0}, dg = 0.0;
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    const double xv = x[j], yv = tm[k4 * 16 + j][r];
+    mx[0] = fmax(mx[0], fabs(xv));
+    mx[1] = fmax(mx[1], fabs(yv));
+    mx[2] = fmax(mx[2], fabs(2.0 * xv - yv));
+    mx[3] = fmax(mx[3], fabs(2.0 * yv - xv));
+    dg += 2.0 * (xv * xv - xv * yv + yv * yv);
+  }
+  // over the row's quad (the four 16-column quarters), in a fixed pattern
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    mx[m] = fmax(mx[m], quad_xor<0xB1>(mx[m]));
+    mx[m] = fmax(mx[m], quad_xor<0x4E>(mx[m]));
+  }
+  dg += quad_xor<0xB1>(dg);
+  dg += quad_xor<0x4E>(dg);
+  if (k4 == 0 && row < n_v) {
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+      atomicMax(tmax + ((size_t)q * 4 + m) * n_v_pad + row, (unsigned long long)__double_as_longlong(mx[m]));
+    dgp[((size_t)q * nt + C) * n_v_pad + row] = dg;
+  }
+}
+
+hipError_t launch_pair_row_stats(const double* T, const int* slot, int n_pairs, int n_v, int n_v_pad,
+                                 unsigned long long* tmax, double* dgp, hipStream_t st) {
+  if (n_pairs <= 0) return hipSuccess;
+  if (n_v_pad % TB != 0 || n_v_pad < n_v) return hipErrorInvalidValue;
+  const int nt = n_v_pad / TB;
+  dim3 grid(nt * nt, n_pairs), block(256);
+  if (n_v % 2 == 0)
+    hipLaunchKernelGGL(pair_row_stats_kernel<true>, grid, block, 0, st, T, slot, n_v, n_v_pad, nt, tmax, dgp);
+  else
+    hipLaunchKernelGGL(pair_row_stats_kernel<false>, grid, block, 0, st, T, slot, n_v, n_v_pad, nt, tmax, dgp);
+  return hipGetLastError();
+}
+
 // diag[a] += sum over pairs q and column blocks of w_q dgp[q][blk][a], in a fixed
 // order (strided per thread, then a fixed tree), so the result is reproducible
 __global__ __launch_bounds__(256) void diag_accumulate_kernel(const double* dgp, const int2* pairs, const double* pw,
@@ -261,9 +321,10 @@ __global__ __launch_bounds__(256) void diag_accumulate_kernel(const double* dgp,
   if (t == 0) diag[a] += red[0];
 }
 
-hipError_t launch_split_t_bf16(const double* T, const int2* pairs, const double* pw, double w, int n_pairs, int n_v,
-                               int n_v_pad, int rows_pad, int ns, const unsigned long long* tmax, const double* dgp,
-                               __bf16* out, double* diag, hipStream_t st) {
+hipError_t launch_split_t_bf16(const double* T, const int* slot, const int2* pairs, const double* pw, double w,
+                               int n_pairs, int n_v, int n_v_pad, int rows_pad, int ns,
+                               const unsigned long long* tmax, const double* dgp, __bf16* out, double* diag,
+                               hipStream_t st) {
   if (n_pairs <= 0) return hipSuccess;
   if (n_v_pad % TB != 0 || n_v_pad < n_v || rows_pad % TB != 0 || rows_pad < n_v_pad) return hipErrorInvalidValue;
   const int nt = n_v_pad / TB;
@@ -273,11 +334,11 @@ hipError_t launch_split_t_bf16(const double* T, const int2* pairs, const double*
 #define SPLIT_T_BF16(NS_)                                                                                          \
   do {                                                                                                             \
     if (vec)                                                                                                       \
-      hipLaunchKernelGGL((split_t_bf16_kernel<NS_, true>), grid, block, 0, st, T, n_v, n_v_pad, rows_pad, nt, tmax, \
-                         out);                                                                                     \
-    else                                                                                                           \
-      hipLaunchKernelGGL((split_t_bf16_kernel<NS_, false>), grid, block, 0, st, T, n_v, n_v_pad, rows_pad, nt,      \
+      hipLaunchKernelGGL((split_t_bf16_kernel<NS_, true>), grid, block, 0, st, T, slot, n_v, n_v_pad, rows_pad, nt, \
                          tmax, out);                                                                               \
+    else                                                                                                           \
+      hipLaunchKernelGGL((split_t_bf16_kernel<NS_, false>), grid, block, 0, st, T, slot, n_v, n_v_pad, rows_pad,    \
+                         nt, tmax, out);                                                                           \
   } while (0)
   switch (ns) {
     case 2: SPLIT_T_BF16(2); break;
@@ -292,9 +353,9 @@ hipError_t launch_split_t_bf16(const double* T, const int2* pairs, const double*
   return hipGetLastError();
 }
 
-hipError_t launch_split_t_i8(const double* T, const int2* pairs, const double* pw, double w, int n_pairs, int n_v,
-                             int n_v_pad, int ns, const unsigned long long* tmax, const double* dgp, int8_t* out,
-                             int* rexp, double* diag, hipStream_t st) {
+hipError_t launch_split_t_i8(const double* T, const int* slot, const int2* pairs, const double* pw, double w,
+                             int n_pairs, int n_v, int n_v_pad, int ns, const unsigned long long* tmax,
+                             const double* dgp, int8_t* out, int* rexp, double* diag, hipStream_t st) {
   if (n_pairs <= 0) return hipSuccess;
   if (n_v_pad % TB != 0 || n_v_pad < n_v) return hipErrorInvalidValue;
   const int nt = n_v_pad / TB;
@@ -304,10 +365,11 @@ hipError_t launch_split_t_i8(const double* T, const int2* pairs, const double* p
 #define SPLIT_T_I8(NS_)                                                                                         \
   do {                                                                                                          \
     if (vec)                                                                                                    \
-      hipLaunchKernelGGL((split_t_i8_kernel<NS_, true>), grid, block, 0, st, T, n_v, n_v_pad, nt, tmax, out, rexp); \
-    else                                                                                                        \
-      hipLaunchKernelGGL((split_t_i8_kernel<NS_, false>), grid, block, 0, st, T, n_v, n_v_pad, nt, tmax, out,    \
+      hipLaunchKernelGGL((split_t_i8_kernel<NS_, true>), grid, block, 0, st, T, slot, n_v, n_v_pad, nt, tmax, out, \
                          rexp);                                                                                 \
+    else                                                                                                        \
+      hipLaunchKernelGGL((split_t_i8_kernel<NS_, false>), grid, block, 0, st, T, slot, n_v, n_v_pad, nt, tmax,   \
+                         out, rexp);                                                                            \
   } while (0)
   switch (ns) {
     case 2: SPLIT_T_I8(2); break;

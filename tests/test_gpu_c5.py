@@ -2,8 +2,11 @@
 2000 virtuals, 6000 auxiliary functions, trace-12 Gamma_act) against the FP64
 oracle's expected values (tests/golden/c5_s0.5.json, written by make_golden.py
 from the oracle alone): energy, every occupation number, the kept count at
-p_o = 0.985 and the correction, for the FP64 path (1e-8 Eh) and the INT8-digit
-mixed path (1e-6 Eh).  The correction E_full - E_kept depends on the natural
+p_o = 0.985 and the correction, for the FP64 path (1e-8 Eh), the split-BF16
+mixed path the benchmark times (four slices for both products, 1e-6 Eh) and the
+INT8-digit mixed path (1e-6 Eh).  After the BF16 build the correction's kept-space
+energy runs on INT8 digits, as in the benchmark: in BF16 that pass alone is off
+by ~2e-6 Eh here (3e-14 of |E_kept|), in INT8 digits by ~5e-8 Eh.  The correction E_full - E_kept depends on the natural
 orbitals, which two FP64 eigensolvers (the library's and LAPACK in the oracle) give
 only to rounding: at |E_kept| ~ 7e7 Eh that alone moves E_kept by ~1e-16 |E_kept|
 per orbital rotation, so the FP64 bound on the correction is max(1e-8, 2e-15
@@ -34,7 +37,9 @@ def test_c5_full_size_against_golden():
     inp = synth.config_inputs("c5")
     d = dp.upload_inputs(inp)
     del inp
-    for precision, tol, occ_tol in ((dp.FP64, 1e-8, 1e-11), (dp.INT8_SLICED, 1e-6, 1e-8)):
+    for precision, tol, occ_tol, corr_precision in ((dp.FP64, 1e-8, 1e-11, dp.FP64),
+                                                    (dp.BF16_SLICED, 1e-6, 1e-8, dp.INT8_SLICED),
+                                                    (dp.INT8_SLICED, 1e-6, 1e-8, dp.INT8_SLICED)):
         print(f"c5: precision {precision}", flush=True)
         opts = dp.make_opts(120, 12, 2000, 6000, 0.5, precision=precision)
         r = dp.build_vv_density(opts, d["eps_hole"], d["eps_vir"], d["gamma_act"], d["B"])
@@ -42,7 +47,8 @@ def test_c5_full_size_against_golden():
         dE = dd_diff((float(e[0]), float(e[1])), gold["energy"])
         t = dp.fno_truncate(r["D_vv"], tr["p_o"])
         occ = t["occ"].cpu().numpy()
-        c = dp.pt2_energy_correction(opts, d["eps_hole"], d["eps_vir"], d["gamma_act"], d["B"], t["no_vecs"],
+        oc = dp.make_opts(120, 12, 2000, 6000, 0.5, precision=corr_precision)
+        c = dp.pt2_energy_correction(oc, d["eps_hole"], d["eps_vir"], d["gamma_act"], d["B"], t["no_vecs"],
                                      t["n_kept"], r["e_pt2"])
         cc = c["correction"].cpu().numpy()
         dC = dd_diff((float(cc[0]), float(cc[1])), tr["correction"])

@@ -101,3 +101,33 @@ def test_bf16_density_reproducible_and_batched():
     assert np.array_equal(a["D"], b["D"]) and a["energy"] == b["energy"]
     c = gpu_pass(inp, 0.5, precision=BF16, pair_batch=7)
     assert np.abs(c["D"] - a["D"]).max() <= 1e-12 * np.abs(a["D"]).max()
+
+
+def test_bf16_range_guard():
+    """A row of B whose largest magnitude lies below the range BF16 slicing keeps
+    exact (2^(E_min - 1), E_min = 8 - (126 - 9 (k - 1)) // 2 = -41 at k = 4 slices)
+    makes the BF16 pass return DFPT2_ERR_UNSUPPORTED instead of losing the bits
+    silently; FP64 and INT8 digits accept the same input, and a row just inside
+    the range passes the guard and stays at parity with the oracle."""
+    dp = need_gpu()
+    from paper_2312_07008_amd._lib import ERR_UNSUPPORTED, DfptError
+    inp = synth.generate(4, 0, 40, 64, seed=11)
+    m = np.abs(inp.B[1, 7]).max()
+    tiny = inp.B.copy()
+    tiny[1, 7] *= 2.0 ** -60 / m                     # max |row| = 2^-60 < 2^-42
+    inside = inp.B.copy()
+    inside[1, 7] *= 2.0 ** -41.5 / m                 # frexp exponent -41 = E_min
+    t = inp.replace(B=tiny)
+    print("range guard: BF16 with a row at 2^-60", flush=True)
+    with pytest.raises(DfptError) as ex:
+        gpu_pass(t, 0.5, precision=BF16)
+    assert ex.value.status == ERR_UNSUPPORTED
+    print(f"  status {ex.value.status}: {ex.value}", flush=True)
+    ref = o.pt2_pass_inputs(t, 0.5)
+    for prec, tol in ((dp.FP64, 1e-12), (dp.INT8_SLICED, 1e-9)):
+        g = gpu_pass(t, 0.5, precision=prec)
+        assert dd_diff(g["energy"], ref.energy) <= tol * abs(ref.E)
+    ok = inp.replace(B=inside)
+    g = gpu_pass(ok, 0.5, precision=BF16)
+    ref = o.pt2_pass_inputs(ok, 0.5)
+    assert dd_diff(g["energy"], ref.energy) <= 1e-9 * abs(ref.E)

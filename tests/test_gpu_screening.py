@@ -145,6 +145,11 @@ def test_learned_screen_gain_over_bound():
     r = o.pt2_pass_inputs(inp, s)
     truth_below = np.sum(np.triu(r.pair_tnorm[:30, :30] < thr))
     assert nd_net >= nd_bnd and nd_net > 0 and nd_net <= truth_below
+    # pair by pair: every pair either screen drops is truly below the threshold
+    for mk in (m_net.cpu().numpy(), m_bnd.cpu().numpy()):
+        wrong = [(i, j, r.pair_tnorm[i, j]) for i in range(inp.n_core) for j in range(i, inp.n_core)
+                 if mk[i, j] == 0 and not r.pair_tnorm[i, j] < thr]
+        assert not wrong, wrong[:5]
     for g in (net, bnd):
         assert dd_diff(g["energy"], full["energy"]) <= 1e-6
         t0 = dp.fno_truncate(full["raw"]["D_vv"], p_o)
