@@ -125,6 +125,30 @@ int dfpt2_build_vv_density(const dfpt2_opts* opts,
                            double* pair_energy, float* pair_tnorm,
                            void* workspace, size_t ws_bytes, dfpt2_stream_t stream);
 
+/*
+ * dfpt2_build_vv_density for callers that cannot allocate device memory: code
+ * under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Same arguments, results and errors as dfpt2_build_vv_density minus the
+ * workspace: the pass runs in the library's static device scratch of
+ * DFPT2_STATIC_SCRATCH_BYTES per GPU (reserved when the library first uses that
+ * GPU, held until the process ends).  The call allocates nothing (leave the
+ * stage timers off: enabled, they create HIP events); a pass whose workspace
+ * (dfpt2_workspace_size) exceeds the scratch returns DFPT2_ERR_WORKSPACE and
+ * launches nothing -- a smaller pair_batch shrinks the need.  The scratch is
+ * shared by every call on one GPU and keeps the last call's contents (the pass
+ * initializes what it reads): calls that overlap on one GPU (other host threads
+ * or streams) race and must be serialized by the caller.  `stream` must belong
+ * to the current device.
+ */
+#define DFPT2_STATIC_SCRATCH_BYTES (64ull << 20)
+int dfpt2_build_vv_density_noalloc(const dfpt2_opts* opts,
+                                   const double* eps_hole, const double* eps_vir,
+                                   const double* gamma_act, const double* B,
+                                   const uint8_t* pair_mask,
+                                   double* D_vv, double* e_pt2,
+                                   double* pair_energy, float* pair_tnorm,
+                                   dfpt2_stream_t stream);
+
 /* Workspace (bytes) for fno_truncate / dfpt2_eigh_sym at dimension n.  bytes: host out. */
 int fno_truncate_workspace_size(int64_t n_vir, size_t* bytes);
 

@@ -14,6 +14,7 @@ ERR_HIP = -3
 ERR_NOT_CONVERGED = -4
 ERR_NONFINITE = -5
 ERR_UNSUPPORTED = -6
+STATIC_SCRATCH_BYTES = 64 << 20  # DFPT2_STATIC_SCRATCH_BYTES
 
 FP64 = 0
 BF16_SLICED = 1
@@ -57,6 +58,8 @@ SIGNATURES = {
     "dfpt2_workspace_size": (_int, [ctypes.POINTER(Opts), ctypes.POINTER(_sz)]),
     "dfpt2_build_vv_density": (_int, [ctypes.POINTER(Opts), _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                                       _vp, _sz, _vp]),
+    "dfpt2_build_vv_density_noalloc": (_int, [ctypes.POINTER(Opts), _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                                              _vp]),
     "fno_truncate_workspace_size": (_int, [_i64, ctypes.POINTER(_sz)]),
     "fno_truncate": (_int, [_vp, _i64, _dbl, _dbl, _vp, _vp, ctypes.POINTER(_i64),
                             ctypes.POINTER(_dbl), _vp, _sz, _vp]),

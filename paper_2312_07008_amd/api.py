@@ -15,7 +15,7 @@ import torch
 from . import _lib
 from ._lib import Opts, check
 
-__all__ = ["make_opts", "workspace_size", "build_vv_density", "fno_truncate_workspace_size",
+__all__ = ["make_opts", "workspace_size", "build_vv_density", "build_vv_density_noalloc", "fno_truncate_workspace_size",
            "fno_truncate", "fno_truncate_rule", "naf_compress", "eigh_sym", "pt2_correction_workspace_size", "pt2_energy_correction",
            "upload_inputs", "profile_enable", "profile_read", "pp_ladder", "pp_ladder_workspace_size",
            "add_active_particle_density", "pairscreen_num_params", "pairscreen_features",
@@ -106,6 +106,36 @@ def build_vv_density(opts: Opts, eps_hole: torch.Tensor, eps_vir: torch.Tensor,
                                      _ptr(B), _ptr(pair_mask), _ptr(D_vv), _ptr(e_pt2), _ptr(pair_energy),
                                      _ptr(pair_tnorm), _ptr(ws), ctypes.c_size_t(ws.numel()),
                                      _stream(stream)))
+    return dict(D_vv=D_vv, e_pt2=e_pt2, pair_energy=pair_energy, pair_tnorm=pair_tnorm)
+
+
+def build_vv_density_noalloc(opts: Opts, eps_hole: torch.Tensor, eps_vir: torch.Tensor,
+                             gamma_act: Optional[torch.Tensor], B: torch.Tensor,
+                             pair_mask: Optional[torch.Tensor] = None, *, D_vv: torch.Tensor,
+                             e_pt2: torch.Tensor, pair_energy=None, pair_tnorm=None, stream=None) -> dict:
+    """dfpt2_build_vv_density_noalloc: the pass in the library's static scratch.
+    Every output is caller-provided (nothing is allocated here either)."""
+    lib = _lib.load()
+    n_h = opts.n_core + opts.n_act
+    n_v, n_aux = opts.n_vir, opts.n_aux
+    _need(eps_hole, "eps_hole", torch.float64, n_h)
+    _need(eps_vir, "eps_vir", torch.float64, n_v)
+    _need(B, "B", torch.float64, n_h * n_v * n_aux)
+    if opts.n_act:
+        _need(gamma_act, "gamma_act", torch.float64, opts.n_act * opts.n_act)
+    else:
+        gamma_act = None
+    if pair_mask is not None:
+        _need(pair_mask, "pair_mask", torch.uint8, n_h * n_h)
+    _need(D_vv, "D_vv", torch.float64, n_v * n_v)
+    _need(e_pt2, "e_pt2", torch.float64, 2)
+    if pair_energy is not None:
+        _need(pair_energy, "pair_energy", torch.float64, n_h * n_h)
+    if pair_tnorm is not None:
+        _need(pair_tnorm, "pair_tnorm", torch.float32, n_h * n_h)
+    check(lib.dfpt2_build_vv_density_noalloc(ctypes.byref(opts), _ptr(eps_hole), _ptr(eps_vir), _ptr(gamma_act),
+                                             _ptr(B), _ptr(pair_mask), _ptr(D_vv), _ptr(e_pt2), _ptr(pair_energy),
+                                             _ptr(pair_tnorm), _stream(stream)))
     return dict(D_vv=D_vv, e_pt2=e_pt2, pair_energy=pair_energy, pair_tnorm=pair_tnorm)
 
 

@@ -6,6 +6,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 
 #include "../../include/dfpt2.h"
@@ -207,6 +208,37 @@ int plan_pass(const dfpt2_opts* o, PassPlan* pl, bool energy_only) {
   return DFPT2_OK;
 }
 
+// Static device scratch of dfpt2_build_vv_density_noalloc: one copy per GPU,
+// held from the first use on that GPU until the process ends.  Host code never
+// passes this name to a kernel or a copy: each device's address comes from
+// hipGetSymbolAddress (static_scratch below) and only that address is used.
+static __device__ __align__(256) char scratch[DFPT2_STATIC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+// Address of the current device's copy of `scratch`, looked up once per device
+// (with that device current) on the first call that needs it.
+static int static_scratch(void** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (dev < 0 || dev >= kMaxDevices) return fail(DFPT2_ERR_UNSUPPORTED, "device %d beyond %d devices", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    if (!ptr) return fail(DFPT2_ERR_HIP, "hipGetSymbolAddress(scratch) returned a null address");
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return DFPT2_OK;
+}
+
 }  // namespace dfpt2
 
 using namespace dfpt2;
@@ -257,6 +289,29 @@ int dfpt2_build_vv_density(const dfpt2_opts* opts, const double* eps_hole, const
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   return run_pass(pl, *opts, eps_hole, eps_vir, gamma_act, B, pair_mask, D_vv, e_pt2, pair_energy, pair_tnorm,
                   static_cast<char*>(workspace), s);
+}
+
+int dfpt2_build_vv_density_noalloc(const dfpt2_opts* opts, const double* eps_hole, const double* eps_vir,
+                                   const double* gamma_act, const double* B, const uint8_t* pair_mask,
+                                   double* D_vv, double* e_pt2, double* pair_energy, float* pair_tnorm,
+                                   dfpt2_stream_t stream) {
+  g_last_error.clear();
+  PassPlan pl;
+  int st = plan_pass(opts, &pl);
+  if (st != DFPT2_OK) return st;
+  if (!eps_hole || !eps_vir || !B || !D_vv || !e_pt2)
+    return fail(DFPT2_ERR_INVALID_ARG, "eps_hole, eps_vir, B, D_vv and e_pt2 must be non-null");
+  if (pl.n_act > 0 && !gamma_act) return fail(DFPT2_ERR_INVALID_ARG, "gamma_act is null but n_act > 0");
+  if (pl.ws_bytes > (size_t)DFPT2_STATIC_SCRATCH_BYTES)
+    return fail(DFPT2_ERR_WORKSPACE,
+                "this pass needs %zu bytes of scratch, more than the %llu of the static scratch; use "
+                "dfpt2_build_vv_density with a workspace, or a smaller pair_batch",
+                pl.ws_bytes, (unsigned long long)DFPT2_STATIC_SCRATCH_BYTES);
+  void* ws = nullptr;
+  if ((st = static_scratch(&ws)) != DFPT2_OK) return st;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  return run_pass(pl, *opts, eps_hole, eps_vir, gamma_act, B, pair_mask, D_vv, e_pt2, pair_energy, pair_tnorm,
+                  static_cast<char*>(ws), s);
 }
 
 }  // extern "C"
