@@ -18,5 +18,7 @@ Modules:
              (Eq. 6), in the full or the truncated virtual space
   a9_active  the Eq. A9 terms whose amplitudes carry an active particle index
              (zero cumulants, no singles)
+  a9_cumulant the first-order singles (Eq. A6) and the remaining Eq. A9 terms:
+             the singles and the terms with the two-body density cumulant
 """
-from . import a9_active, dsrg_pt2, ladder, naf, screening  # noqa: F401
+from . import a9_active, a9_cumulant, dsrg_pt2, ladder, naf, screening  # noqa: F401

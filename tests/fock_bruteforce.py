@@ -48,44 +48,157 @@ def _occupation_probabilities(n_modes, probs):
     return diag
 
 
-def brute_force_pt2(eps_core, eps_act, eps_vir, gamma_act, B, s, B_act=None):
-    """Return (E2, Gamma_vv) by explicit Fock-space traces.
+def singlet_pair_states(n_act, coeffs):
+    """Two-electron singlet states of the active orbitals in their own Jordan-Wigner
+    space (2 n_act modes, spin orbital 2 u + sigma): psi = sum_uv C_uv a+_{u up} a+_{v dn} |0>
+    with C symmetric (a singlet) and normalized.  coeffs: list of symmetric C."""
+    c = _jw_annihilators(2 * n_act)
+    vac = np.zeros(2 ** (2 * n_act))
+    vac[0] = 1.0
+    out = []
+    for C in coeffs:
+        C = 0.5 * (C + C.T)
+        psi = np.zeros_like(vac)
+        for u in range(n_act):
+            for v in range(n_act):
+                psi += C[u, v] * (c[2 * u].T @ (c[2 * v + 1].T @ vac))
+        out.append(psi / np.linalg.norm(psi))
+    return out
+
+
+def active_rdms(n_act, weights, states):
+    """Spin-free active 1-RDM gamma_u^v, 2-cumulant lambda_uv^xy and 3-cumulant
+    lambda_uvw^xyz of the ensemble sum_a w_a |psi_a><psi_a| (states from
+    singlet_pair_states).  Spin-orbital cumulants by the usual subtraction of
+    antisymmetrized products, spin-free ones as sums over matching spins."""
+    n = 2 * n_act
+    c = [x.toarray() for x in _jw_annihilators(n)]
+    cd = [x.T for x in c]
+
+    def ev(op):
+        return sum(w * psi @ (op @ psi) for w, psi in zip(weights, states))
+
+    g1 = np.array([[ev(cd[p] @ c[q]) for q in range(n)] for p in range(n)])
+    g2 = np.zeros((n,) * 4)
+    for p in range(n):
+        for q in range(n):
+            pq = cd[p] @ cd[q]
+            for r in range(n):
+                for t in range(n):
+                    g2[p, q, r, t] = ev(pq @ c[t] @ c[r])   # <a+_p a+_q a_t a_r> = gamma^pq_rt
+    g3 = np.zeros((n,) * 6)
+    for p in range(n):
+        for q in range(n):
+            for r in range(n):
+                pqr = cd[p] @ cd[q] @ cd[r]
+                if not np.any(pqr):
+                    continue
+                for x in range(n):
+                    for y in range(n):
+                        for z in range(n):
+                            g3[p, q, r, x, y, z] = ev(pqr @ c[z] @ c[y] @ c[x])
+    l2 = g2 - np.einsum("pr,qs->pqrs", g1, g1) + np.einsum("ps,qr->pqrs", g1, g1)
+    # gamma3 = l3 + A(g1 l2) + A(g1 g1 g1): all ways of giving one upper and one lower
+    # index to a factor, with the sign of the permutation of the lower indices
+    import itertools
+    perms = list(itertools.permutations(range(3)))
+
+    def sign(pm):
+        s_, pm = 1, list(pm)
+        for i in range(3):
+            for j in range(i + 1, 3):
+                if pm[i] > pm[j]:
+                    s_ = -s_
+        return s_
+
+    up = "pqr"
+    lo = "xyz"
+    a1l2 = np.zeros_like(g3)
+    a111 = np.zeros_like(g3)
+    for pm in perms:
+        sg = sign(pm)
+        lw = "".join(lo[k] for k in pm)     # lower index given to each upper position
+        a111 += sg * np.einsum(f"{up[0]}{lw[0]},{up[1]}{lw[1]},{up[2]}{lw[2]}->pqrxyz", g1, g1, g1)
+        # one upper index (position i) with its lower partner in g1, the other two in l2
+        for i in range(3):
+            rest = [k for k in range(3) if k != i]
+            a1l2 += sg * np.einsum(f"{up[i]}{lw[i]},{up[rest[0]]}{up[rest[1]]}{lw[rest[0]]}{lw[rest[1]]}->pqrxyz",
+                                   g1, l2) / 2.0
+    l3 = g3 - a1l2 - a111
+    # spin-free sums over matching spins (spin orbital 2 u + sigma)
+    G = g1.reshape(n_act, 2, n_act, 2)
+    gamma = np.einsum("usvs->uv", G)
+    L2 = l2.reshape(n_act, 2, n_act, 2, n_act, 2, n_act, 2)
+    lam2 = np.einsum("asbtcsdt->abcd", L2)
+    L3 = l3.reshape((n_act, 2) * 6)
+    lam3 = np.einsum("asbtcrdsetfr->abcdef", L3)
+    return gamma, lam2, lam3, dict(g1=g1, g2=g2, g3=g3, l2=l2, l3=l3)
+
+
+def brute_force_pt2(eps_core, eps_act, eps_vir, gamma_act, B, s, B_act=None, states=None, singles=None,
+                    probe_singles_source=False):
+    """Return (E2, Gamma_vv, gamma_act) by explicit Fock-space traces.
 
     Spatial orbitals: core, active, virtual.  Spin orbital index 2 p + sigma.
-    B_act [n_h, n_act, n_aux]: with it, active particle indices are included."""
+    B_act [n_h, n_act, n_aux]: with it, active particle indices are included.
+    states: None for the quasi-free reference with active 1-RDM gamma_act, or
+    (weights, vectors) of a correlated ensemble over the active orbitals (vectors in
+    the active orbitals' own Jordan-Wigner space, singlet_pair_states), the core
+    doubly occupied and the virtuals empty; gamma_act is then ignored.
+    singles: None, or t1[i, e] = t_e^i, spin-free singles amplitudes of hole i and
+    virtual e added to the cluster operator as sum_sigma t_e^i a+_{e sigma} a_{i sigma}.
+    probe_singles_source (quasi-free reference only): instead, return src[i, e, sigma],
+    the coefficient of {a+_{e sigma} a_{i sigma}} in the one-body part of [H0, T2]
+    (the first-order source of the singles), read off the generalized Wick theorem:
+    for a quasi-free reference <{a+_i a_e} X> = sum_q gamma^i_q X^e_q, since a one-body
+    normal-ordered string cannot fully contract with a two-body one; core holes have
+    gamma^m_q = delta_mq, active holes are solved for with the active 1-RDM."""
     n_c, n_a, n_v = len(eps_core), len(eps_act), len(eps_vir)
     n_h = n_c + n_a
     n_sp = n_h + n_v
     n_modes = 2 * n_sp
     eps = np.concatenate([eps_core, eps_act, eps_vir])
-
-    # natural orbitals of the active block: Gamma_act = U diag(n) U^T
-    if n_a:
-        occ_nat, U = np.linalg.eigh(gamma_act)
-    else:
-        occ_nat, U = np.zeros(0), np.zeros((0, 0))
-    # c_k: annihilators of natural spin orbitals (Jordan-Wigner modes)
     c = _jw_annihilators(n_modes)
-    probs = np.zeros(n_modes)
-    for p in range(n_c):
-        probs[2 * p] = probs[2 * p + 1] = 1.0
-    for k in range(n_a):
-        probs[2 * (n_c + k)] = probs[2 * (n_c + k) + 1] = occ_nat[k] / 2.0
-    rho = sp.diags(_occupation_probabilities(n_modes, probs), format="csr")
 
-    # semicanonical annihilators: a_(u sigma) = sum_k U_uk c_(k sigma)
-    a = list(c)
-    for ui in range(n_a):
-        for sig in range(2):
-            op = None
-            for k in range(n_a):
-                term = U[ui, k] * c[2 * (n_c + k) + sig]
-                op = term if op is None else op + term
-            a[2 * (n_c + ui) + sig] = op.tocsr()
+    if states is None:
+        # natural orbitals of the active block: Gamma_act = U diag(n) U^T
+        if n_a:
+            occ_nat, U = np.linalg.eigh(gamma_act)
+        else:
+            occ_nat, U = np.zeros(0), np.zeros((0, 0))
+        # c_k: annihilators of natural spin orbitals (Jordan-Wigner modes)
+        probs = np.zeros(n_modes)
+        for p in range(n_c):
+            probs[2 * p] = probs[2 * p + 1] = 1.0
+        for k in range(n_a):
+            probs[2 * (n_c + k)] = probs[2 * (n_c + k) + 1] = occ_nat[k] / 2.0
+        rho = sp.diags(_occupation_probabilities(n_modes, probs), format="csr")
+
+        # semicanonical annihilators: a_(u sigma) = sum_k U_uk c_(k sigma)
+        a = list(c)
+        for ui in range(n_a):
+            for sig in range(2):
+                op = None
+                for k in range(n_a):
+                    term = U[ui, k] * c[2 * (n_c + k) + sig]
+                    op = term if op is None else op + term
+                a[2 * (n_c + ui) + sig] = op.tocsr()
+
+        def tr(x):
+            return float((rho @ x).diagonal().sum())
+    else:
+        # |core filled> (x) |psi_active> (x) |virtuals empty> in the full Jordan-Wigner basis
+        weights, vecs = states
+        core = np.zeros(2 ** (2 * n_c))
+        core[-1] = 1.0
+        virt = np.zeros(2 ** (2 * n_v))
+        virt[0] = 1.0
+        full = [np.kron(np.kron(core, v), virt) for v in vecs]
+        a = list(c)
+
+        def tr(x):
+            return float(sum(w * f @ (x @ f) for w, f in zip(weights, full)))
     ad = [x.T.tocsr() for x in a]
-
-    def tr(x):
-        return float((rho @ x).diagonal().sum())
 
     # spatial integrals (ai|bj) = sum_Q B^Q_ia B^Q_jb, written with explicit indices
     Vsp = np.einsum("iaQ,jbQ->ijab", B, B)
@@ -152,6 +265,33 @@ def brute_force_pt2(eps_core, eps_act, eps_vir, gamma_act, B, s, B_act=None):
                     ex = excitation(A_, B_, I_, J_)
                     T = t * ex if T is None else T + t * ex
                     Vop = v * ex if Vop is None else Vop + v * ex
+    if probe_singles_source:
+        assert states is None and singles is None
+        H0p = None
+        for p_ in range(n_sp):
+            for sig in range(2):
+                k = 2 * p_ + sig
+                term = eps[p_] * (ad[k] @ a[k])
+                H0p = term if H0p is None else H0p + term
+        X = (H0p @ T - T @ H0p).tocsr()
+        src = np.zeros((n_h, n_v, 2))
+        ga = gamma_act / 2.0                                 # per-spin active 1-RDM
+        for e_ in range(n_v):
+            for sig in range(2):
+                ke = 2 * (n_h + e_) + sig
+                probe = [tr(ad[2 * i_ + sig] @ a[ke] @ X) for i_ in range(n_h)]
+                src[:n_c, e_, sig] = probe[:n_c]
+                if n_a:
+                    src[n_c:, e_, sig] = np.linalg.solve(ga, np.array(probe[n_c:]))
+        return src
+    if singles is not None:
+        for i_ in range(n_h):
+            for e_ in range(n_v):
+                if singles[i_, e_] == 0.0:
+                    continue
+                for sig in range(2):
+                    ex = ad[2 * (n_h + e_) + sig] @ a[2 * i_ + sig]     # {a+_e a_i}: gamma^e_i = 0
+                    T = singles[i_, e_] * ex if T is None else T + singles[i_, e_] * ex
     Aop = (T - T.T).tocsr()
     Vop = (Vop + Vop.T).tocsr()
     H0 = None
