@@ -220,6 +220,39 @@ int dfpt2_add_active_particle_density(const dfpt2_opts* opts, const double* eps_
                                       const double* gamma_act, const double* B, const double* B_act, double* D_vv,
                                       void* workspace, size_t ws_bytes, dfpt2_stream_t stream);
 
+/* Workspace (bytes) for dfpt2_add_cumulant_singles_density, with (with_lambda != 0)
+ * or without a cumulant.  bytes: host out. */
+int dfpt2_cumulant_singles_workspace_size(const dfpt2_opts* opts, int with_lambda, size_t* bytes);
+
+/*
+ * Adds to D_vv the Eq. A9 terms with the first-order singles and with the two-body
+ * density cumulant lambda of the reference:
+ *     2 t_e^m t_f^m + t_e^u t_f^v gamma_u^v + (t_e^u t_fv^xy + t_ey^uv t_f^x) lambda_uv^xy
+ *   + t_ee'^uv t_fe'^xy lambda_uv^xy + P(t_ey^mv t_fu^mx) lambda_uv^xy
+ *   + 1/2 t_ez^uv t_fw^xy eta_w^z lambda_uv^xy + 1/2 P(t_ey^wv t_fu^zx) gamma_w^z lambda_uv^xy
+ * (t_ab^ij the amplitude of a+_a a+_b a_j a_i; m core, u..z active, e, f, e' virtual;
+ * eta = 2 - gamma; P(t_ap^ij t_cd^kq) = 2 t_ap^ij t_cd^kq - t_ap^ij t_cd^qk - t_ap^ji t_cd^kq
+ * - t_aq^ji t_cd^pk), with the singles of Eq. A6 in the semicanonical model (f_ai = 0):
+ *     t_e^i = 1/2 sum_ux (eps_x - eps_u) gamma_x^u (2 t_ex^iu - t_ex^ui) (1 - e^{-s D^2}) / D,
+ *     D = eps_i - eps_e.
+ * The three-body-cumulant term is left out, as in the method (Sec. 2).  Together with
+ * dfpt2_build_vv_density and dfpt2_add_active_particle_density this is every term of
+ * Eq. A9 but that one.
+ *   opts        as for dfpt2_add_active_particle_density
+ *   eps_hole, eps_vir, gamma_act, B, B_act   as for dfpt2_add_active_particle_density
+ *   lambda_act  [n_act^4] spin-free cumulant lambda_uv^xy at [((u n_act + v) n_act + x) n_act + y],
+ *               symmetric under (u v)(x y) -> (v u)(y x) and (u v) <-> (x y); NULL adds only the
+ *               singles terms
+ *   D_vv        [n_vir][n_vir] in/out: the terms are added, symmetrized
+ *   t1          [n_h][n_vir] out or NULL: the singles t_e^i (row i)
+ * Does nothing when n_act = 0 (no source for singles, no cumulant).  FP64 throughout.
+ * Asynchronous on the stream.  Errors: INVALID_ARG, WORKSPACE, HIP.
+ */
+int dfpt2_add_cumulant_singles_density(const dfpt2_opts* opts, const double* eps_hole, const double* eps_vir,
+                                       const double* gamma_act, const double* lambda_act, const double* B,
+                                       const double* B_act, double* D_vv, double* t1, void* workspace,
+                                       size_t ws_bytes, dfpt2_stream_t stream);
+
 /* Workspace (bytes) for naf_compress (sizes from opts).  bytes: host out. */
 int naf_compress_workspace_size(const dfpt2_opts* opts, size_t* bytes);
 

@@ -103,26 +103,25 @@ def cumulant_singles_density(eps_core, eps_act, eps_vir, gamma_act, lam, B, B_ac
         W2 = np.einsum("uvey,uvxy->ex", Xaa, lam)
         D += tu.T @ W1.T + W2 @ tu
     if 3 in terms:
-        D += np.einsum("uvea,xyfa,uvxy->ef", Tv, Tv, lam)
+        D += np.einsum("uvea,xyfa,uvxy->ef", Tv, Tv, lam, optimize=True)
     if 4 in terms:
         # P( t_ey^mv t_fu^mx ) lambda_uv^xy over core m, with (p, q) = (y, x):
         # 2 t_ey^mv t_fu^mx - t_ey^mv t_fu^xm - t_ey^vm t_fu^mx - t_ex^vm t_fu^ym
         for m in range(n_core):
             a_mv, a_vm = Xca[m], Xac[:, m]          # [v, e, y] = t_ey^mv and t_ey^vm
-            prod = (2.0 * np.einsum("vey,xfu->vyxuef", a_mv, a_mv)
-                    - np.einsum("vey,xfu->vyxuef", a_mv, a_vm)
-                    - np.einsum("vey,xfu->vyxuef", a_vm, a_mv)
-                    - np.einsum("vex,yfu->vyxuef", a_vm, a_vm))
-            D += np.einsum("vyxuef,uvxy->ef", prod, lam)
+            D += 2.0 * np.einsum("vey,xfu,uvxy->ef", a_mv, a_mv, lam, optimize=True)
+            D -= np.einsum("vey,xfu,uvxy->ef", a_mv, a_vm, lam, optimize=True)
+            D -= np.einsum("vey,xfu,uvxy->ef", a_vm, a_mv, lam, optimize=True)
+            D -= np.einsum("vex,yfu,uvxy->ef", a_vm, a_vm, lam, optimize=True)
     if 5 in terms:
-        D += 0.5 * np.einsum("uvez,xyfw,wz,uvxy->ef", Xaa, Xaa, eta, lam)
+        D += 0.5 * np.einsum("uvez,xyfw,wz,uvxy->ef", Xaa, Xaa, eta, lam, optimize=True)
     if 6 in terms:
-        # 1/2 P( t_ey^wv t_fu^zx ) gamma_w^z lambda_uv^xy, all holes active
-        t_1 = 2.0 * np.einsum("wvey,zxfu->wvyzxuef", Xaa, Xaa)
-        t_2 = np.einsum("wvey,xzfu->wvyzxuef", Xaa, Xaa)
-        t_3 = np.einsum("vwey,zxfu->wvyzxuef", Xaa, Xaa)
-        t_4 = np.einsum("vwex,yzfu->wvyzxuef", Xaa, Xaa)
-        D += 0.5 * np.einsum("wvyzxuef,wz,uvxy->ef", t_1 - t_2 - t_3 - t_4, G, lam)
+        # 1/2 P( t_ey^wv t_fu^zx ) gamma_w^z lambda_uv^xy, all holes active:
+        # 2 t_ey^wv t_fu^zx - t_ey^wv t_fu^xz - t_ey^vw t_fu^zx - t_ex^vw t_fu^yz
+        D += 0.5 * (2.0 * np.einsum("wvey,zxfu,wz,uvxy->ef", Xaa, Xaa, G, lam, optimize=True)
+                    - np.einsum("wvey,xzfu,wz,uvxy->ef", Xaa, Xaa, G, lam, optimize=True)
+                    - np.einsum("vwey,zxfu,wz,uvxy->ef", Xaa, Xaa, G, lam, optimize=True)
+                    - np.einsum("vwex,yzfu,wz,uvxy->ef", Xaa, Xaa, G, lam, optimize=True))
     return D
 
 
@@ -133,4 +132,4 @@ def three_cumulant_term(eps_core, eps_act, eps_vir, B, B_act, lam3, s):
     n_core = len(eps_core)
     X, _ = _amplitude_blocks(eps_h, eps_act, eps_vir, B, B_act, s)
     Xaa = X[n_core:, n_core:]
-    return np.einsum("uwez,xyfv,xyzuvw->ef", Xaa, Xaa, lam3)
+    return np.einsum("uwez,xyfv,xyzuvw->ef", Xaa, Xaa, lam3, optimize=True)

@@ -68,6 +68,9 @@ SIGNATURES = {
     "dfpt2_eigh_sym": (_int, [_vp, _i64, _vp, _vp, _vp, _sz, _vp]),
     "dfpt2_active_particle_workspace_size": (_int, [ctypes.POINTER(Opts), ctypes.POINTER(_sz)]),
     "dfpt2_add_active_particle_density": (_int, [ctypes.POINTER(Opts), _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "dfpt2_cumulant_singles_workspace_size": (_int, [ctypes.POINTER(Opts), _int, ctypes.POINTER(_sz)]),
+    "dfpt2_add_cumulant_singles_density": (_int, [ctypes.POINTER(Opts), _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                                                  _sz, _vp]),
     "pp_ladder_workspace_size": (_int, [_i64, _i64, _i64, _i64, ctypes.POINTER(_sz)]),
     "pp_ladder": (_int, [_i64, _i64, _i64, _vp, _vp, _vp, _i64, _i64, _vp, _vp, _sz, _vp]),
     "naf_compress_workspace_size": (_int, [ctypes.POINTER(Opts), ctypes.POINTER(_sz)]),

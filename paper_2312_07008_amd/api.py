@@ -15,7 +15,7 @@ import torch
 from . import _lib
 from ._lib import Opts, check
 
-__all__ = ["make_opts", "workspace_size", "build_vv_density", "build_vv_density_noalloc", "fno_truncate_workspace_size",
+__all__ = ["make_opts", "add_cumulant_singles_density", "workspace_size", "build_vv_density", "build_vv_density_noalloc", "fno_truncate_workspace_size",
            "fno_truncate", "fno_truncate_rule", "naf_compress", "eigh_sym", "pt2_correction_workspace_size", "pt2_energy_correction",
            "upload_inputs", "profile_enable", "profile_read", "pp_ladder", "pp_ladder_workspace_size",
            "add_active_particle_density", "pairscreen_num_params", "pairscreen_features",
@@ -226,6 +226,31 @@ def add_active_particle_density(opts: Opts, eps_hole, eps_vir, gamma_act, B, B_a
     check(lib.dfpt2_add_active_particle_density(ctypes.byref(opts), _ptr(eps_hole), _ptr(eps_vir), _ptr(gamma_act),
                                                 _ptr(B), _ptr(B_act), _ptr(D_vv), _ptr(ws),
                                                 ctypes.c_size_t(ws.numel()), _stream(stream)))
+    return D_vv
+
+
+def add_cumulant_singles_density(opts: Opts, eps_hole, eps_vir, gamma_act, lambda_act, B, B_act, D_vv, *,
+                                 t1=None, workspace=None, stream=None) -> torch.Tensor:
+    """D_vv += the Eq. A9 terms with the singles (Eq. A6) and, if lambda_act is given,
+    with the two-body cumulant; t1 [n_h, n_vir] (optional) receives the singles."""
+    lib = _lib.load()
+    n_h, n_v, n_a, n_aux = opts.n_core + opts.n_act, opts.n_vir, opts.n_act, opts.n_aux
+    _need(eps_hole, "eps_hole", torch.float64, n_h)
+    _need(eps_vir, "eps_vir", torch.float64, n_v)
+    _need(gamma_act, "gamma_act", torch.float64, n_a * n_a)
+    if lambda_act is not None:
+        _need(lambda_act, "lambda_act", torch.float64, n_a ** 4)
+    _need(B, "B", torch.float64, n_h * n_v * n_aux)
+    _need(B_act, "B_act", torch.float64, n_h * n_a * n_aux)
+    _need(D_vv, "D_vv", torch.float64, n_v * n_v)
+    if t1 is not None:
+        _need(t1, "t1", torch.float64, n_h * n_v)
+    n = ctypes.c_size_t(0)
+    check(lib.dfpt2_cumulant_singles_workspace_size(ctypes.byref(opts), int(lambda_act is not None), ctypes.byref(n)))
+    ws = _workspace(int(n.value), D_vv.device, workspace)
+    check(lib.dfpt2_add_cumulant_singles_density(ctypes.byref(opts), _ptr(eps_hole), _ptr(eps_vir), _ptr(gamma_act),
+                                                 _ptr(lambda_act), _ptr(B), _ptr(B_act), _ptr(D_vv), _ptr(t1),
+                                                 _ptr(ws), ctypes.c_size_t(ws.numel()), _stream(stream)))
     return D_vv
 
 

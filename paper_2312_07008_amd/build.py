@@ -30,6 +30,7 @@ SOURCES = [
     "naf.cpp",
     "ladder.cpp",
     "active_particle.hip",
+    "cumulant.hip",
     "split.hip",
     "pair_bf16_v.hip",
     "pair_fp8.hip",

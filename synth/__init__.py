@@ -44,6 +44,13 @@ the active-hole / active-particle block symmetrized, B^Q_{n_c+u, x} and
 B^Q_{n_c+x, u} both replaced by their sum over sqrt(2) (B^Q_ux = B^Q_xu, as
 density-fitted integrals are).
 
+Two-body density cumulant of the active orbitals (``active_cumulant``, a
+separate stream ``default_rng(seed)``): G ~ N(0,1) with shape (n_act,)*4, made
+symmetric under the simultaneous swap of both index pairs and under the exchange
+of the pairs, lambda = c (G + G^(vu yx)) / 2 then (lambda + lambda^(xy uv)) / 2,
+with c = 0.1 (the size of the cumulants of a correlated few-electron reference;
+no other structure is imposed, the terms that consume it being linear in it).
+
 Particle-particle ladder inputs (``ladder_inputs``, a separate stream
 ``default_rng(seed)``): virtual energies U[0.1, 5.0] sorted; Z ~ N(0,1) with
 C-order shape (n_aux, n_v, n_v); W ~ N(0,1) with shape (n_amp, n_v, n_v);
@@ -64,7 +71,7 @@ from typing import Optional
 
 import numpy as np
 
-__all__ = ["Inputs", "generate", "CONFIGS", "config_inputs", "input_recipe", "mlp_init"]
+__all__ = ["Inputs", "generate", "CONFIGS", "config_inputs", "input_recipe", "mlp_init", "active_cumulant"]
 
 
 @dataclasses.dataclass
@@ -213,6 +220,13 @@ def mlp_init(seed: int = 0, hidden: int = 64, n_in: int = 5) -> np.ndarray:
     W2 = rng.standard_normal((hidden, hidden)) / np.sqrt(hidden)
     w3 = rng.standard_normal(hidden) / np.sqrt(hidden)
     return np.concatenate([W1.ravel(), np.zeros(hidden), W2.ravel(), np.zeros(hidden), w3, [0.0]])
+
+
+def active_cumulant(n_act: int, seed: int = 0, scale: float = 0.1) -> np.ndarray:
+    """lam[u, v, x, y] (= lambda_uv^xy) following the recipe in the module docstring."""
+    g = np.random.default_rng(seed).standard_normal((n_act,) * 4)
+    lam = 0.5 * scale * (g + g.transpose(1, 0, 3, 2))
+    return np.ascontiguousarray(0.5 * (lam + lam.transpose(2, 3, 0, 1)))
 
 
 @dataclasses.dataclass
