@@ -45,6 +45,9 @@ WORKLOADS = {
     "c3": dict(base="c3", gen=dict()),
     "c2": dict(base="c2", gen=dict(low_rank=64)),
     "c5": dict(base="c5", gen=dict()),
+    # the screened variant of the largest one-GPU instance: c5 sizes, localized holes and
+    # auxiliary functions (xi = 1.25)
+    "c5loc": dict(base="c5", gen=dict(localized_xi=1.25)),
     # c3 sizes with a redundant auxiliary set (rank 2000 of 4000 up to 1e-7 noise): the
     # input natural auxiliary functions compress (--naf-scan)
     "c4naf": dict(base="c4", gen=dict(aux_rank=2000, aux_noise=1e-7)),
@@ -166,6 +169,25 @@ def active_particle_bench(args, wl, cfg):
                         "unit": "TFLOP/s", "frac": flops / (ms * 1e-3) / 1e12 / PEAK_TFLOPS["f64"],
                         "traffic": None, "kernel": "gemm_f64 (amplitudes, eta, rank update) + mixing kernels"}}
     log(f"active-particle terms: {ms:.2f} ms, {res['tflops']:.1f} TFLOP/s")
+    # the singles (Eq. A6) and the two-body-cumulant terms of Eq. A9, with a synthetic cumulant
+    lam = torch.from_numpy(synth.active_cumulant(n_act, 0)).cuda()
+    ncs = dp.add_cumulant_singles_density
+    for _ in range(args.warmup):
+        ncs(opts, d["eps_hole"], d["eps_vir"], d["gamma_act"], lam, d["B"], d["B_act"], D)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(args.steps):
+        ncs(opts, d["eps_hole"], d["eps_vir"], d["gamma_act"], lam, d["B"], d["B_act"], D)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms2 = e0.elapsed_time(e1) / args.steps
+    kl = 2 * n_h * n_act ** 2 + n_act ** 3 + n_h + 2 * n_act
+    f2 = (2.0 * n_v * n_h * n_h * n_act * n_aux + 2.0 * n_v * n_v * n_act * n_act * n_aux
+          + 2.0 * n_v * n_act ** 4 * n_v + 2.0 * n_v * n_v * (kl + n_act * n_act * n_v))
+    res["cumulant_singles"] = {"ms": ms2, "gemm_flops": f2, "tflops": f2 / (ms2 * 1e-3) / 1e12,
+                               "frac_of_f64_peak": f2 / (ms2 * 1e-3) / 1e12 / PEAK_TFLOPS["f64"],
+                               "terms": "Eq. A6 singles and the Eq. A9 terms with singles or the two-body cumulant"}
+    log(f"singles + cumulant terms: {ms2:.2f} ms, {res['cumulant_singles']['tflops']:.1f} TFLOP/s")
     print(json.dumps(res), flush=True)
 
 
@@ -489,7 +511,7 @@ def main():
     kname = {"int8": "i8"}.get(args.precision, args.precision)
     split_epi = prof["pair_epilogue"][1] > 0
     if split_epi:
-        kid, kdesc = f"pair_v_bf16_kernel<{ns1},4>", "pair_v_bf16 (V = B_i B_j^T, 128 x 128 tiles"
+        kid, kdesc = f"pair_v_bf16_kernel<{ns1},4,4>", "pair_v_bf16 (V = B_i B_j^T, 128 x 128 tiles"
     else:
         kid = f"pair_gemm_{kname}_kernel<{ns1},true>"
         kdesc = f"pair_gemm_{kname if ns1 > 1 else 'f64'} (V = B_i B_j^T with the fused DSRG epilogue"
