@@ -36,6 +36,7 @@ SOURCES = [
     "pair_fp8.hip",
     "pair_i8.hip",
     "split_t.hip",
+    "epi_split_bf16.hip",
     "density_bf16.hip",
     "density_i8.hip",
     "active.hip",

@@ -179,7 +179,10 @@ int plan_pass(const dfpt2_opts* o, PassPlan* pl, bool energy_only) {
   p.off_Texp = take(p.ns2 >= 2 && p.precision == DFPT2_INT8_SLICED ? sizeof(int) * 4 * (size_t)nb_t * p.n_v_pad_d
                                                                     : 0);
   p.off_dg = take(p.ns2 >= 2 ? sizeof(double) * (size_t)nb_t * (p.n_v_pad_d / 64) * p.n_v_pad_d : 0);
-  p.off_tmax = take(p.ns2 >= 2 ? sizeof(unsigned long long) * 4 * (size_t)nb_t * p.n_v_pad_d : 0);
+  // row maxima: INT8 digits only (the BF16 slices take one exponent per 64-column block from the block)
+  p.off_tmax = take(p.ns2 >= 2 && p.precision == DFPT2_INT8_SLICED
+                        ? sizeof(unsigned long long) * 4 * (size_t)nb_t * p.n_v_pad_d
+                        : 0);
   p.off_diag = take(p.ns2 >= 2 ? sizeof(double) * (size_t)p.n_v : 0);
   // active holes: stacked amplitude/integral matrices before and after the rotation
   if (p.n_act > 0) {
@@ -337,7 +340,7 @@ hipError_t launch_pair(const PairLaunch& L, const PairKernelArgs& a, int n_pairs
   b.Vr = a.Vr;
   b.epart = a.epart;
   b.tpart = a.tpart;
-  b.tmax = (L.precision == DFPT2_BF16_SLICED || L.precision == DFPT2_INT8_SLICED) ? a.tmax : nullptr;
+  b.tmax = (L.precision == DFPT2_INT8_SLICED) ? a.tmax : nullptr;
   b.dgp = b.tmax ? a.dgp : nullptr;
   b.n_v = a.n_v;
   b.n_v_pad = L.n_v_pad;
@@ -349,6 +352,13 @@ hipError_t launch_pair(const PairLaunch& L, const PairKernelArgs& a, int n_pairs
   b.e_weight = a.e_weight;
   if (L.precision == DFPT2_FP8_SLICED) return launch_pair_gemm_fp8(b, L.ns, n_pairs, st);
   if (L.precision == DFPT2_INT8_SLICED) return launch_pair_gemm_i8(b, L.ns, n_pairs, st);
+  if (L.ts && b.T && !b.Vr) {  // split-BF16 density: V in b.T, then the epilogue that slices the amplitudes
+    const hipError_t e = launch_pair_v_bf16(b, L.ns, n_pairs, st);
+    if (e != hipSuccess) return e;
+    if (product) product->close();
+    ProfScope ps(DFPT2_STAGE_PAIR_EPILOGUE, st);
+    return launch_pair_epi_split_bf16(b, n_pairs, L.ns2, L.rows_t, L.ts, L.dgp, st);
+  }
   if (b.T || b.Vr) {  // amplitudes stored: product and epilogue as two kernels
     const hipError_t e = launch_pair_v_bf16(b, L.ns, n_pairs, st);
     if (e != hipSuccess) return e;
@@ -375,14 +385,14 @@ static int sliced_density(const PassPlan& pl, const double* T, const int* slot, 
   auto* tmax = reinterpret_cast<unsigned long long*>(ws + pl.off_tmax);
   double* dgp = reinterpret_cast<double*>(ws + pl.off_dg);
   double* diag = reinterpret_cast<double*>(ws + pl.off_diag);
-  {
-    ProfScope ps(DFPT2_STAGE_SPLIT_T, s);
-    if ((e = launch_fill(reinterpret_cast<double*>(tmax), (size_t)np * 4 * pl.n_v_pad_d, 0.0, s)) != hipSuccess)
-      return hip_fail(e, "fill");
-    if ((e = launch_pair_row_stats(T, slot, np, pl.n_v, pl.n_v_pad_d, tmax, dgp, s)) != hipSuccess)
-      return hip_fail(e, "amplitude row data");
-  }
   if (pl.precision == DFPT2_INT8_SLICED) {
+    {  // one exponent per row: the row maxima first
+      ProfScope ps(DFPT2_STAGE_SPLIT_T, s);
+      if ((e = launch_fill(reinterpret_cast<double*>(tmax), (size_t)np * 4 * pl.n_v_pad_d, 0.0, s)) != hipSuccess)
+        return hip_fail(e, "fill");
+      if ((e = launch_pair_row_stats(T, slot, np, pl.n_v, pl.n_v_pad_d, tmax, dgp, s)) != hipSuccess)
+        return hip_fail(e, "amplitude row data");
+    }
     int8_t* Ts = reinterpret_cast<int8_t*>(ws + pl.off_Ts);
     int* Texp = reinterpret_cast<int*>(ws + pl.off_Texp);
     {
@@ -412,8 +422,8 @@ static int sliced_density(const PassPlan& pl, const double* T, const int* slot, 
   __bf16* Ts = reinterpret_cast<__bf16*>(ws + pl.off_Ts);
   {
     ProfScope ps(DFPT2_STAGE_SPLIT_T, s);
-    if ((e = launch_split_t_bf16(T, slot, pairs, pw, 1.0, np, pl.n_v, pl.n_v_pad_d, pl.n_v_rows_t, pl.ns2, tmax, dgp,
-                                 Ts, diag, s)) != hipSuccess)
+    if ((e = launch_split_t_bf16(T, slot, pairs, pw, 1.0, np, pl.n_v, pl.n_v_pad_d, pl.n_v_rows_t, pl.ns2, dgp, Ts,
+                                 diag, s)) != hipSuccess)
       return hip_fail(e, "amplitude split");
   }
   DensitySlicedArgs ds{};
@@ -585,6 +595,12 @@ int run_pass(const PassPlan& pl, const dfpt2_opts& o, const double* eps_h, const
 
   PairLaunch L{pl.precision, pl.ns1, B, nullptr, nullptr, nullptr, pl.n_v_pad, pl.n_aux_pad, nullptr};
   if (pl.energy_only && pl.precision == DFPT2_BF16_SLICED) L.vbuf = reinterpret_cast<double*>(ws + pl.off_T);
+  if (!pl.energy_only && pl.precision == DFPT2_BF16_SLICED && pl.ns2 >= 2) {
+    L.ts = reinterpret_cast<__bf16*>(ws + pl.off_Ts);
+    L.dgp = reinterpret_cast<double*>(ws + pl.off_dg);
+    L.ns2 = pl.ns2;
+    L.rows_t = pl.n_v_rows_t;
+  }
   // d_count[0]: pairs of the mask; d_count[1]: set by the BF16 split when a row of B
   // lies below the range its slices need (both read back with one copy below)
   if ((e = launch_fill(reinterpret_cast<double*>(d_count), 2, 0.0, s)) != hipSuccess) return hip_fail(e, "fill");
@@ -668,7 +684,7 @@ int run_pass(const PassPlan& pl, const dfpt2_opts& o, const double* eps_h, const
   for (int p0 = 0, b = 0; p0 < count; p0 += pl.batch, ++b) {
     const int np = (count - p0 < pl.batch) ? count - p0 : pl.batch;
     pa.pairs = pairs + p0;
-    if (pl.ns2 >= 2) {  // row maxima and diagonal partials for the split-BF16 density
+    if (pl.ns2 >= 2 && pl.precision == DFPT2_INT8_SLICED) {  // row maxima and diagonal partials for the digits
       pa.tmax = reinterpret_cast<unsigned long long*>(ws + pl.off_tmax);
       pa.dgp = reinterpret_cast<double*>(ws + pl.off_dg);
       ProfScope ps(DFPT2_STAGE_SPLIT_T, s);
@@ -712,14 +728,13 @@ int run_pass(const PassPlan& pl, const dfpt2_opts& o, const double* eps_h, const
       if ((e = launch_density_i8(dd, pl.ns2, s)) != hipSuccess) return hip_fail(e, "density kernel (INT8)");
       continue;
     }
-    if (pl.ns2 >= 2) {
-      __bf16* Ts = reinterpret_cast<__bf16*>(ws + pl.off_Ts);
+    if (pl.ns2 >= 2) {  // the epilogue wrote the slices and the diagonal partials
+      __bf16* Ts = L.ts;
       {
         ProfScope ps(DFPT2_STAGE_SPLIT_T, s);
-        if ((e = launch_split_t_bf16(T, nullptr, pairs + p0, nullptr, pl.w_density, np, pl.n_v, pl.n_v_pad_d, pl.n_v_rows_t,
-                                     pl.ns2, pa.tmax, pa.dgp, Ts, reinterpret_cast<double*>(ws + pl.off_diag), s)) !=
-            hipSuccess)
-          return hip_fail(e, "amplitude split");
+        if ((e = launch_diag_accumulate(L.dgp, pairs + p0, nullptr, pl.w_density, np, pl.n_v, pl.n_v_pad_d,
+                                        reinterpret_cast<double*>(ws + pl.off_diag), s)) != hipSuccess)
+          return hip_fail(e, "density diagonal");
       }
       DensitySlicedArgs ds{};
       ds.Ts = Ts;
@@ -750,7 +765,10 @@ int run_pass(const PassPlan& pl, const dfpt2_opts& o, const double* eps_h, const
     }
   }
   if (pl.n_act > 0) {
-    int st = run_active_blocks(pl, o, eps_h, eps_v, gamma_act, L, Dpart, pair_energy, pair_tnorm, ws, s);
+    PairLaunch La = L;  // the active blocks store FP64 amplitudes and rotate them
+    La.ts = nullptr;
+    La.dgp = nullptr;
+    int st = run_active_blocks(pl, o, eps_h, eps_v, gamma_act, La, Dpart, pair_energy, pair_tnorm, ws, s);
     if (st != DFPT2_OK) return st;
   }
   {

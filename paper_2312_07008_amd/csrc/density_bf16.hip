@@ -5,13 +5,14 @@
 // Per unordered pair the contribution is X1 Y1^T + X2 Y2^T (split_t.hip gives
 // the slices of the rows of X1 = T, X2 = T^T, Y1 = 2T - T^T, Y2 = 2T^T - T).
 // As in the pair kernel, the slice products of level s + t - 1 <= NS are kept.
-// Within one product of one pair every product of a row a of X and a row b of Y
-// is an integer multiple of one unit (the two rows' scales), so the level-1 and
-// level-2 sums are exact in FP32 over 128 contraction steps; they are added into
-// FP64 every 128 steps and at the end of each of the pair's two products (with
-// the pair's weight), and levels >= 3 are summed in FP32 per product.  The two
-// products carry different units, so the contraction runs over X1 / Y1 first
-// and X2 / Y2 after it, with one set of accumulators.  D is symmetric: only
+// The operands carry one exponent per (row, 64-column block), so within one
+// block of one product of one pair every product of a row a of X and a row b of
+// Y is an integer multiple of one unit (the two rows' block scales): the level-1
+// and level-2 sums are exact in FP32 over the block's 64 contraction steps and
+// are added into FP64 at the end of every block (with the pair's weight);
+// levels >= 3 are summed in FP32 per product.  The two products carry different
+// units, so the contraction runs over X1 / Y1 first and X2 / Y2 after it, with
+// one set of accumulators.  D is symmetric: only
 // tiles on or above the diagonal are formed.  Diagonal elements are left out:
 // split_t.hip sums them exactly in FP64 (the rows of X and Y there carry the
 // same amplitudes, so the dropped slice products would not average out).
@@ -47,7 +48,7 @@ constexpr int SLOTS = 8;
 constexpr int KB_X = TX / 8, KB_Y = TY / 8;  // kilobytes of the two panels per chunk
 constexpr int KB_W = (KB_X + KB_Y) / 4;      // kilobytes per wave per chunk
 constexpr int PY = KB_X * 64;                // u4 offset of the Y panel in a buffer
-constexpr int FLUSH_CHUNKS = 128 / KC;
+constexpr int FLUSH_CHUNKS = 64 / KC;  // one exponent block of the operands
 typedef uint32_t u4 __attribute__((ext_vector_type(4)));
 typedef __attribute__((address_space(3))) void lds_void;
 typedef __attribute__((address_space(1))) void gbl_void;

@@ -63,6 +63,12 @@ struct PairLaunch {
   int n_v_pad, n_aux_pad;
   const double* norm2;
   double* vbuf = nullptr;  // BF16 energy-only passes: V of one batch for the epilogue kernel
+  // BF16 passes with the split-BF16 density: the epilogue writes the density
+  // operands' slices (ns2 per operand, matrices rows_t rows apart) to ts and the
+  // diagonal partials to dgp instead of storing FP64 amplitudes
+  __bf16* ts = nullptr;
+  double* dgp = nullptr;
+  int ns2 = 0, rows_t = 0;
 };
 class ProfScope;
 // `product` (may be null): the caller's timer of the pair product; where the

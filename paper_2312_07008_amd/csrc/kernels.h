@@ -14,7 +14,7 @@ struct PairKernelArgs {
   double* Vr;           // [n_pairs][n_v][n_v] renormalized integrals out, or null
   double* epart;        // [n_pairs][nTP] energy partial per tile pair, or null
   double* tpart;        // [n_pairs][nTP] ||T||^2 partial per tile pair, or null
-  unsigned long long* tmax;  // split-BF16 only, or null: row maxima for the density slices (PairSlicedArgs)
+  unsigned long long* tmax;  // INT8 digits only, or null: row maxima for the density digits (PairSlicedArgs)
   double* dgp;               // with tmax: diagonal partial sums
   int n_v, n_aux, nt, nTP;
   double s;
@@ -37,7 +37,7 @@ struct PairSlicedArgs {
   double* Vr;           // [n_pairs][n_v][n_v] renormalized integrals out, or null
   double* epart;
   double* tpart;
-  unsigned long long* tmax;  // BF16 / INT8 only, or null: [n_pairs][4][n_v_pad] row maxima for the density slices
+  unsigned long long* tmax;  // INT8 only, or null: [n_pairs][4][n_v_pad] row maxima for the density digits
   double* dgp;               // with tmax: [n_pairs][nt][n_v_pad] diagonal partial sums (split_t.hip)
   int n_v, n_v_pad, n_aux_pad, nt, nTP;  // n_v_pad: slab rows of Bs; nt: 64-wide tiles of n_v;
                                         // nTP: workgroup tiles per pair
@@ -51,6 +51,12 @@ struct PairSlicedArgs {
 // (store) or only forms the energy partials (!store)
 hipError_t launch_pair_v_bf16(const PairSlicedArgs& a, int ns, int n_pairs, hipStream_t st);
 hipError_t launch_pair_epi_bf16(const PairSlicedArgs& a, int n_pairs, bool store, hipStream_t st);
+// the epilogue of the split-BF16 density pass (epi_split_bf16.hip): from the V in
+// a.T, the energy and norm partials as above, and instead of T the ns2 BF16 slices
+// of the four density operands (layout of launch_split_t_bf16, matrices rows_pad
+// rows apart) in Ts and the diagonal partials in dgp ([n_pairs][nt][n_v_pad_d])
+hipError_t launch_pair_epi_split_bf16(const PairSlicedArgs& a, int n_pairs, int ns2, int rows_pad, __bf16* Ts,
+                                      double* dgp, hipStream_t st);
 hipError_t launch_pair_gemm_fp8(const PairSlicedArgs& a, int ns, int n_pairs, hipStream_t st);
 hipError_t launch_pair_gemm_i8(const PairSlicedArgs& a, int ns, int n_pairs, hipStream_t st);
 // largest n_aux_pad for which the INT8 level sums stay exact with ns digits
@@ -94,19 +100,22 @@ struct DensitySlicedArgs {
 // workgroup tiles (128 x 64, on or above the diagonal) of the split-BF16 density kernel
 int density_bf16_tiles(int nt);
 // slices of the four density operands of every pair of a batch (T: [n_pairs][n_v][n_v]),
-// from the row maxima tmax ([n_pairs][4][n_v_pad]) the pair kernel recorded, plus
-// diag[a] += the exact FP64 diagonal of the batch's contribution from the pair
-// kernel's partial sums dgp ([n_pairs][n_v_pad/64][n_v_pad]); the operand matrices
-// are rows_pad rows apart (a multiple of 64, >= n_v_pad); rows n_v .. n_v_pad - 1
-// are written as zeros, rows n_v_pad .. rows_pad - 1 are not written
-// (slot: matrix q is T + slot[q] n_v^2, or T + q n_v^2 when slot is null)
+// one exponent per (row, 64-column block) taken from the block itself, plus the
+// exact FP64 diagonal partials dgp ([n_pairs][n_v_pad/64][n_v_pad]) and diag[a] +=
+// their weighted sum; the operand matrices are rows_pad rows apart (a multiple of
+// 64, >= n_v_pad); rows n_v .. n_v_pad - 1 are written as zeros, rows
+// n_v_pad .. rows_pad - 1 are not written (slot: matrix q is T + slot[q] n_v^2, or
+// T + q n_v^2 when slot is null)
 hipError_t launch_split_t_bf16(const double* T, const int* slot, const int2* pairs, const double* pw, double w,
-                               int n_pairs, int n_v, int n_v_pad, int rows_pad, int ns,
-                               const unsigned long long* tmax, const double* dgp, __bf16* out, double* diag,
-                               hipStream_t st);
+                               int n_pairs, int n_v, int n_v_pad, int rows_pad, int ns, double* dgp, __bf16* out,
+                               double* diag, hipStream_t st);
+// diag[a] += sum over the pairs q and 64-column blocks of w_q dgp[q][blk][a]
+// (w_q = w pw[q], halved for i == j), in a fixed order
+hipError_t launch_diag_accumulate(const double* dgp, const int2* pairs, const double* pw, double w, int n_pairs,
+                                  int n_v, int n_v_pad, double* diag, hipStream_t st);
 // row maxima of the four density operands (tmax, atomic max: zero it first) and the
 // diagonal partials (dgp) of amplitude matrices T + slot[q] n_v^2 that did not come
-// out of a pair-kernel epilogue
+// out of a pair-kernel epilogue, for the INT8-digit split
 hipError_t launch_pair_row_stats(const double* T, const int* slot, int n_pairs, int n_v, int n_v_pad,
                                  unsigned long long* tmax, double* dgp, hipStream_t st);
 hipError_t launch_density_bf16(const DensitySlicedArgs& a, int ns, hipStream_t st);

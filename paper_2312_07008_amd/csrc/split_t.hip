@@ -7,135 +7,53 @@
 //     m = 1:  X2[a][c] = T[c][a]
 //     m = 2:  Y1[b][c] = 2 T[b][c] - T[c][b]
 //     m = 3:  Y2[b][c] = 2 T[c][b] - T[b][c]
-// Every row of the four matrices is split like a row of B (split.hip): scale
-// 2^E from the row's largest magnitude, ns true-scale BF16 slices whose integer
-// digits s_t (|s_t| <= 256) satisfy sum_t s_t 512^(ns-t) = rint(x 2^(8 + 9(ns-1) - E)),
-// so the density kernel can sum the slice products of one pair exactly in FP32.
-// The digits are taken from that rounded integer with balanced base-512 digit
-// extraction, which gives the same represented value as slicing by successive
-// round-to-nearest steps.  Output per pair q: [q][m][rows_pad][n_v_pad/16][ns][16]
-// (rows and columns n_v .. n_v_pad - 1 are zeros), the chunk-interleaved layout
-// of B's slices.  The matrix stride rows_pad >= n_v_pad lets the density kernel
-// load 128-row panels; rows n_v_pad .. rows_pad - 1 are not written (the density
-// kernel's waves that load them form no products from them).
+// BF16 slices (split_t_bf16_kernel): every row of the four matrices is split
+// per 64-column block, from the largest magnitude of the row within the block
+// (amp_tile.h), into ns true-scale BF16 slices whose integer digits satisfy
+// sum_t s_t 512^(ns-1-t) = rint(x 2^(8 + 9(ns-1) - E)), so the density kernel can
+// sum the slice products of one pair and one block exactly in FP32.  The kernel
+// takes the block maxima itself: every workgroup holds whole 64-column blocks of
+// its rows.  Output per pair q: [q][m][rows_pad][n_v_pad/16][ns][16] (rows and
+// columns n_v .. n_v_pad - 1 are zeros), the chunk-interleaved layout of B's
+// slices.  The matrix stride rows_pad >= n_v_pad lets the density kernel load
+// 128-row panels; rows n_v_pad .. rows_pad - 1 are not written (the density
+// kernel's waves that load them form no products from them).  The main pass
+// forms the same slices in the pair epilogue (epi_split_bf16.hip); this kernel
+// serves amplitude matrices already in memory (the active blocks).
 //
 // The diagonal of the pair's contribution, w_q sum_c (X1 Y1 + X2 Y2)[a][c] =
-// w_q sum_c 2 (x^2 - x y + y^2) with x = T[a][c], y = T[c][a], is summed here in
-// FP64: on the diagonal the rows of X and Y carry the same amplitudes, so the
-// slice products the density kernel drops would not average out there, and the
-// diagonal carries the trace of D.  The density kernel leaves the diagonal out.
+// w_q sum_c 2 (x^2 - x y + y^2) with x = T[a][c], y = T[c][a], is summed in
+// FP64, one partial per (row, 64-column block) in dgp, and accumulated in a
+// fixed order by diag_accumulate_kernel: on the diagonal the rows of X and Y
+// carry the same amplitudes, so the slice products the density kernel drops
+// would not average out there, and the diagonal carries the trace of D.  The
+// density kernel leaves the diagonal out.
 //
-// The four row maxima and the diagonal partial sums come from the pair kernel's
-// epilogue (pair_epilogue.h), which holds every amplitude once.  Here one kernel
-// writes the slices and one workgroup per virtual a then sums the diagonal
-// partials in a fixed order.
+// INT8 digits (split_t_i8_kernel) keep one exponent per row: the four row maxima
+// and the diagonal partial sums come from the pair kernel's epilogue
+// (pair_epilogue.h) or from pair_row_stats_kernel.
 #include <cmath>
 
+#include "amp_tile.h"
 #include "common.h"
 #include "kernels.h"
 
 namespace dfpt2 {
 
-namespace {
-constexpr int TB = 64;
-constexpr int LD = TB + 1;
-typedef uint32_t u4 __attribute__((ext_vector_type(4)));
-
-// value of the lane k ^ 1 (CTRL = 0xB1, quad_perm [1,0,3,2]) or k ^ 2 (0x4E,
-// [2,3,0,1]) of the lane's quad, by DPP moves of the two halves
-template <int CTRL>
-__device__ inline double quad_xor(double v) {
-  const long long b = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_mov_dpp((int)b, CTRL, 0xf, 0xf, false);
-  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xf, 0xf, false);
-  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
-
-// Amplitudes of workgroup (row block A, column block C) of pair matrix Tp: the
-// mirror tile tm[r][c] = T[C*64 + r][A*64 + c] (whole-row loads) and, for thread
-// (row r = tid / 4, quarter k4 = tid % 4), x[j] = T[A*64 + r][C*64 + 16 k4 + j];
-// zeros outside n_v.  VEC (n_v even): rows start 16-byte aligned and columns
-// come in pairs below n_v, so both are read with 16-byte loads (these kernels are
-// bound by the vector-load data path).  Ends with a barrier.
-template <bool VEC>
-__device__ inline void load_amplitudes(const double* Tp, int n_v, int A, int C, double (*tm)[LD], double* x) {
-  const int tid = threadIdx.x;
-  if (VEC) {
-    for (int e = tid; e < TB * TB / 2; e += 256) {
-      const int r = e >> 5, c = 2 * (e & 31);
-      const int hr = C * TB + r, hc = A * TB + c;
-      const double2 v = (hr < n_v && hc < n_v) ? *reinterpret_cast<const double2*>(Tp + (size_t)hr * n_v + hc)
-                                               : make_double2(0.0, 0.0);
-      tm[r][c] = v.x;
-      tm[r][c + 1] = v.y;
-    }
-  } else {
-    for (int e = tid; e < TB * TB; e += 256) {
-      const int r = e >> 6, c = e & 63;
-      const int hr = C * TB + r, hc = A * TB + c;
-      tm[r][c] = (hr < n_v && hc < n_v) ? Tp[(size_t)hr * n_v + hc] : 0.0;
-    }
-  }
-  const int row = A * TB + (tid >> 2), k4 = tid & 3;
-  if (VEC) {
-    // lane k4 of the row's quad reads 16-byte piece 4 j + k4 of the row's 64
-    // columns, so the quad reads 64 contiguous bytes per load; the quad then
-    // transposes the pieces (exchange rounds with partners k4 ^ 1 and k4 ^ 2) so
-    // that lane k4 holds pieces 8 k4 .. 8 k4 + 7, i.e. columns 16 k4 .. + 15
-    const double* src = Tp + (size_t)row * n_v + C * TB;
-    double2 pc[8];
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const int c0 = 2 * (4 * j + k4);
-      pc[j] = (row < n_v && C * TB + c0 < n_v) ? *reinterpret_cast<const double2*>(src + c0) : make_double2(0.0, 0.0);
-    }
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      double2 m[4] = {pc[h], pc[2 + h], pc[4 + h], pc[6 + h]};  // lane k4: pieces 8 t + 4 h + k4
-#pragma unroll
-      for (int k = 1; k <= 2; k <<= 1) {
-        const bool hi = (k4 & k) != 0;
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          if (t & k) continue;
-          const double2 snd = hi ? m[t] : m[t | k];
-          double2 rcv;
-          rcv.x = k == 1 ? quad_xor<0xB1>(snd.x) : quad_xor<0x4E>(snd.x);
-          rcv.y = k == 1 ? quad_xor<0xB1>(snd.y) : quad_xor<0x4E>(snd.y);
-          if (hi) m[t] = rcv;
-          else m[t | k] = rcv;
-        }
-      }
-#pragma unroll
-      for (int t = 0; t < 4; ++t) {  // now piece 8 k4 + 4 h + t
-        x[2 * (4 * h + t)] = m[t].x;
-        x[2 * (4 * h + t) + 1] = m[t].y;
-      }
-    }
-  } else {
-#pragma unroll
-    for (int j = 0; j < 16; ++j) {
-      const int gc = C * TB + k4 * 16 + j;
-      x[j] = (row < n_v && gc < n_v) ? Tp[(size_t)row * n_v + gc] : 0.0;
-    }
-  }
-  __syncthreads();
-}
-}  // namespace
+using amp::LD;
+using amp::TB;
+using amp::u4;
 
 // ---------------------------------------------------------------- slices
 // Workgroup = (row block A, column block C, pair q): rows A x columns C of the
-// four matrices.  x = T[a][c] comes straight from global memory (thread = row,
-// 16-column quarter; when n_v is even, 16-byte loads in which the four threads
-// of a row read 64 contiguous bytes, then a transpose within the four),
-// y = T[c][a] from the mirror tile T[C, A] staged in LDS.  The thread's 16
+// four matrices.  x = T[a][c] comes straight from global memory, y = T[c][a]
+// from the mirror tile T[C, A] staged in LDS (amp::load_tile).  The thread's 16
 // columns are exactly one 16-wide chunk of the output row, so its slices of each
 // matrix (32 NS contiguous bytes) are stored straight from registers; the four
 // threads of a row write 128 NS contiguous bytes.
 template <int NS, bool VEC>
 __global__ __launch_bounds__(256) void split_t_bf16_kernel(const double* T, const int* slot, int n_v, int n_v_pad,
-                                                           int rows_pad, int nt, const unsigned long long* tmax,
-                                                           __bf16* out) {
+                                                           int rows_pad, int nt, double* dgp, __bf16* out) {
   __shared__ double tm[TB][LD];  // T[C-block row][A-block col]
   const int A = blockIdx.x / nt, C = blockIdx.x - (blockIdx.x / nt) * nt, q = blockIdx.y;
   const double* Tp = T + (size_t)(slot ? slot[q] : q) * n_v * n_v;
@@ -143,38 +61,17 @@ __global__ __launch_bounds__(256) void split_t_bf16_kernel(const double* T, cons
   const int r = tid >> 2, k4 = tid & 3;
   const int row = A * TB + r;
   double x[16];
-  load_amplitudes<VEC>(Tp, n_v, A, C, tm, x);
+  amp::load_tile<VEC>(Tp, n_v, A, C, tm, x, true);
   double y[16];
 #pragma unroll
   for (int j = 0; j < 16; ++j) y[j] = tm[k4 * 16 + j][r];
-
-  const size_t row_elems = (size_t)n_v_pad * NS;
+  const size_t row_elems = (size_t)n_v_pad * NS, mat_elems = (size_t)rows_pad * row_elems;
+  __bf16* dst[4];
 #pragma unroll
-  for (int m = 0; m < 4; ++m) {
-    const double mx = __longlong_as_double((long long)tmax[((size_t)q * 4 + m) * n_v_pad + row]);
-    int E = 0;
-    if (mx > 0.0) frexp(mx, &E);
-    bf8v sl[NS][2];
-#pragma unroll
-    for (int j = 0; j < 16; ++j) {
-      const double v = m == 0 ? x[j] : m == 1 ? y[j] : m == 2 ? 2.0 * x[j] - y[j] : 2.0 * y[j] - x[j];
-      long long Z = (mx > 0.0) ? (long long)rint(ldexp(v, 8 + 9 * (NS - 1) - E)) : 0;
-#pragma unroll
-      for (int t = NS - 1; t >= 0; --t) {
-        const int d = t ? (int)(((Z + 256) & 511) - 256) : (int)Z;
-        Z = (Z - d) >> 9;
-        sl[t][j >> 3][j & 7] = (__bf16)ldexpf((float)d, E - 8 - 9 * t);
-      }
-    }
-    // chunk C * 4 + k4 of row `row` of matrix m: [NS][16] bf16
-    u4* dst = reinterpret_cast<u4*>(out + ((size_t)q * 4 + m) * rows_pad * row_elems + (size_t)row * row_elems +
-                                    (size_t)(C * 4 + k4) * (NS * 16));
-#pragma unroll
-    for (int t = 0; t < NS; ++t) {
-      dst[2 * t] = __builtin_bit_cast(u4, sl[t][0]);
-      dst[2 * t + 1] = __builtin_bit_cast(u4, sl[t][1]);
-    }
-  }
+  for (int m = 0; m < 4; ++m)
+    dst[m] = out + ((size_t)q * 4 + m) * mat_elems + (size_t)row * row_elems + (size_t)(C * 4 + k4) * (NS * 16);
+  const double dg = amp::split_block_row<NS>(x, y, dst);
+  if (k4 == 0 && row < n_v) dgp[((size_t)q * nt + C) * n_v_pad + row] = dg;
 }
 
 // ---------------------------------------------------------------- INT8 digits
@@ -196,7 +93,7 @@ __global__ __launch_bounds__(256) void split_t_i8_kernel(const double* T, const 
   const int r = tid >> 2, k4 = tid & 3;
   const int row = A * TB + r;
   double x[16];
-  load_amplitudes<VEC>(Tp, n_v, A, C, tm, x);
+  amp::load_tile<VEC>(Tp, n_v, A, C, tm, x, true);
   double y[16];
 #pragma unroll
   for (int j = 0; j < 16; ++j) y[j] = tm[k4 * 16 + j][r];
@@ -257,7 +154,7 @@ __global__ __launch_bounds__(256) void pair_row_stats_kernel(const double* T, co
   const int r = tid >> 2, k4 = tid & 3;
   const int row = A * TB + r;
   double x[16];
-  load_amplitudes<VEC>(Tp, n_v, A, C, tm, x);
+  amp::load_tile<VEC>(Tp, n_v, A, C, tm, x, true);
   double mx[4] = {0.0, 0.0, 0.0, 0.0}, dg = 0.0;
 #pragma unroll
   for (int j = 0; j < 16; ++j) {
@@ -271,11 +168,11 @@ __global__ __launch_bounds__(256) void pair_row_stats_kernel(const double* T, co
   // over the row's quad (the four 16-column quarters), in a fixed pattern
 #pragma unroll
   for (int m = 0; m < 4; ++m) {
-    mx[m] = fmax(mx[m], quad_xor<0xB1>(mx[m]));
-    mx[m] = fmax(mx[m], quad_xor<0x4E>(mx[m]));
+    mx[m] = fmax(mx[m], amp::quad_xor<0xB1>(mx[m]));
+    mx[m] = fmax(mx[m], amp::quad_xor<0x4E>(mx[m]));
   }
-  dg += quad_xor<0xB1>(dg);
-  dg += quad_xor<0x4E>(dg);
+  dg += amp::quad_xor<0xB1>(dg);
+  dg += amp::quad_xor<0x4E>(dg);
   if (k4 == 0 && row < n_v) {
 #pragma unroll
     for (int m = 0; m < 4; ++m)
@@ -321,10 +218,18 @@ __global__ __launch_bounds__(256) void diag_accumulate_kernel(const double* dgp,
   if (t == 0) diag[a] += red[0];
 }
 
+hipError_t launch_diag_accumulate(const double* dgp, const int2* pairs, const double* pw, double w, int n_pairs,
+                                  int n_v, int n_v_pad, double* diag, hipStream_t st) {
+  if (n_pairs <= 0) return hipSuccess;
+  if (n_v_pad % TB != 0 || n_v_pad < n_v) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(diag_accumulate_kernel, dim3(n_v), dim3(256), 0, st, dgp, pairs, pw, w, n_pairs, n_v_pad / TB,
+                     n_v_pad, diag);
+  return hipGetLastError();
+}
+
 hipError_t launch_split_t_bf16(const double* T, const int* slot, const int2* pairs, const double* pw, double w,
-                               int n_pairs, int n_v, int n_v_pad, int rows_pad, int ns,
-                               const unsigned long long* tmax, const double* dgp, __bf16* out, double* diag,
-                               hipStream_t st) {
+                               int n_pairs, int n_v, int n_v_pad, int rows_pad, int ns, double* dgp, __bf16* out,
+                               double* diag, hipStream_t st) {
   if (n_pairs <= 0) return hipSuccess;
   if (n_v_pad % TB != 0 || n_v_pad < n_v || rows_pad % TB != 0 || rows_pad < n_v_pad) return hipErrorInvalidValue;
   const int nt = n_v_pad / TB;
@@ -335,10 +240,10 @@ hipError_t launch_split_t_bf16(const double* T, const int* slot, const int2* pai
   do {                                                                                                             \
     if (vec)                                                                                                       \
       hipLaunchKernelGGL((split_t_bf16_kernel<NS_, true>), grid, block, 0, st, T, slot, n_v, n_v_pad, rows_pad, nt, \
-                         tmax, out);                                                                               \
+                         dgp, out);                                                                                \
     else                                                                                                           \
       hipLaunchKernelGGL((split_t_bf16_kernel<NS_, false>), grid, block, 0, st, T, slot, n_v, n_v_pad, rows_pad,    \
-                         nt, tmax, out);                                                                           \
+                         nt, dgp, out);                                                                            \
   } while (0)
   switch (ns) {
     case 2: SPLIT_T_BF16(2); break;
@@ -348,9 +253,7 @@ hipError_t launch_split_t_bf16(const double* T, const int* slot, const int2* pai
   }
 #undef SPLIT_T_BF16
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(diag_accumulate_kernel, dim3(n_v), dim3(256), 0, st, dgp, pairs, pw, w, n_pairs, nt, n_v_pad,
-                     diag);
-  return hipGetLastError();
+  return launch_diag_accumulate(dgp, pairs, pw, w, n_pairs, n_v, n_v_pad, diag, st);
 }
 
 hipError_t launch_split_t_i8(const double* T, const int* slot, const int2* pairs, const double* pw, double w,

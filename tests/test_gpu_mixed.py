@@ -79,9 +79,15 @@ def test_bf16_density_slices():
     scale = np.abs(ref.D_vv).max()
     g64 = gpu_pass(inp, 0.5, precision=BF16, slices_gemm2=1)
     errs = []
+    e_split = None
     for k in (2, 3, 4):
         g = gpu_pass(inp, 0.5, precision=BF16, slices_gemm2=k)
-        assert g["energy"] == g64["energy"]            # the energy does not involve the density product
+        # the energy does not involve the density product: bitwise the same for every
+        # slice count; against the FP64-density pass (whose epilogue stores FP64
+        # amplitudes and sums each tile's energy terms in another order) up to rounding
+        e_split = e_split or g["energy"]
+        assert g["energy"] == e_split
+        assert dd_diff(g["energy"], g64["energy"]) <= 1e-14 * abs(g64["energy"][0])
         assert np.array_equal(g["D"], g["D"].T)
         errs.append(np.abs(g["D"] - ref.D_vv).max() / scale)
     print("relative D errors by density slice count:", errs,
