@@ -473,7 +473,7 @@ def main():
         c = dp.pt2_energy_correction(opts_corr, d["eps_hole"], d["eps_vir"], d["gamma_act"], d["B"], tr["no_vecs"],
                                      tr["n_kept"], e, workspace=ws_corr, stream=stream)
         ev[4].record(stream)
-        return ev, tr, c, nd
+        return ev, tr, c, nd, mask
 
     for _ in range(args.warmup):
         step()
@@ -501,12 +501,15 @@ def main():
     # 2 n_v^2 n_aux per computed unordered core pair and per operand-slice product
     ns1 = {"fp64": 1, "int8": 5}.get(args.precision, 4)
     products = ns1 * (ns1 + 1) // 2
-    tr, c, nd = records[-1][1], records[-1][2], records[-1][3]
+    tr, c, nd, mk = records[-1][1], records[-1][2], records[-1][3], records[-1][4]
     n_up = n_core * (n_core + 1) // 2
     computed = n_up - nd
+    # computed pairs i == j: V^{ii} is symmetric, so its algorithmic count is the triangle
+    n_diag = n_core if mk is None else int(torch.diagonal(mk)[:n_core].sum().item())
+    alg_flops = products * n_aux * (2.0 * n_v * n_v * (computed - n_diag) + n_v * (n_v + 1.0) * n_diag)
     pk_ms, pk_launch = prof["pair"]
     screen_drops = nd > 0  # a different set of launches than the counters were taken on
-    achieved = (products * 2.0 * n_v * n_v * n_aux * computed * args.steps) / (pk_ms * 1e-3) / 1e12 if pk_launch else None
+    achieved = (alg_flops * args.steps) / (pk_ms * 1e-3) / 1e12 if pk_launch else None
     peak = PEAK_TFLOPS[dtype]
     kname = {"int8": "i8"}.get(args.precision, args.precision)
     split_epi = prof["pair_epilogue"][1] > 0
@@ -524,7 +527,8 @@ def main():
                 "kernel_ms_per_launch": pk_ms / pk_launch if pk_launch else None,
                 "launches_per_pass": pk_launch // args.steps if pk_launch else 0,
                 "epilogue_ms_per_launch": (prof["pair_epilogue"][0] / prof["pair_epilogue"][1]) if split_epi else None,
-                "flops_per_unit": f"{products} x 2 n_v^2 n_aux per computed unordered core pair"}
+                "flops_per_unit": f"{products} x 2 n_v^2 n_aux per computed unordered core pair i < j, "
+                                  f"{products} x n_v (n_v + 1) n_aux per pair i = j (the triangle of the symmetric V^ii)"}
 
     E = e.cpu().numpy()
     corr = c["correction"].cpu().numpy()
@@ -599,7 +603,7 @@ def main():
         t8 = dp.fno_truncate(D8, p_o)
         E8 = e8.cpu().numpy()
         pk8_ms, pk8_n = p8["pair"]
-        ach8 = (15 * 2.0 * n_v * n_v * n_aux * computed * 2) / (pk8_ms * 1e-3) / 1e12 if pk8_n else None
+        ach8 = (15 / products * alg_flops * 2) / (pk8_ms * 1e-3) / 1e12 if pk8_n else None
         out["alt_int8"] = {"ms_per_pass": statistics.median(times8), "n_kept": t8["n_kept"],
                            "pair_kernel_ms_per_launch": pk8_ms / pk8_n if pk8_n else None,
                            "pair_kernel_TOPs": ach8, "pair_kernel_frac_of_int8_peak": ach8 / PEAK_TFLOPS["i8"]

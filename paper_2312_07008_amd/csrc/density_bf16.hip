@@ -229,14 +229,24 @@ __global__ __launch_bounds__(256, 2) void density_bf16_kernel(DensitySlicedArgs 
   double* Dp = a.Dpart + (size_t)split * n_v * n_v;
   const int gb = J * TY + wc * 32 + r32;
   if (gb < n_v) {
+    // all reads of the old tile first (rows beyond n_v read row n_v - 1 and are
+    // not written back), so that they are in flight together
+    if (a.accumulate) {
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int ga = I * TX + wr * 64 + b * 32 + 8 * (r >> 2) + 4 * hq + (r & 3);
+          dD[b][r] += Dp[(size_t)min(ga, n_v - 1) * n_v + gb];
+        }
+    }
 #pragma unroll
     for (int b = 0; b < 2; ++b)
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         const int ga = I * TX + wr * 64 + b * 32 + 8 * (r >> 2) + 4 * hq + (r & 3);
-        if (ga >= n_v || ga == gb) continue;  // the diagonal comes from the exact FP64 sum (split_t.hip)
-        double* dst = Dp + (size_t)ga * n_v + gb;
-        *dst = a.accumulate ? *dst + dD[b][r] : dD[b][r];
+        // the diagonal comes from the exact FP64 sum of the amplitude split
+        if (ga < n_v && ga != gb) Dp[(size_t)ga * n_v + gb] = dD[b][r];
       }
   }
 }

@@ -11,7 +11,12 @@ orbitals, which two FP64 eigensolvers (the library's and LAPACK in the oracle) g
 only to rounding: at |E_kept| ~ 7e7 Eh that alone moves E_kept by ~1e-16 |E_kept|
 per orbital rotation, so the FP64 bound on the correction is max(1e-8, 2e-15
 |E_kept|) Eh (1.3e-7 Eh here).  About a minute on an MI355X, most of it drawing
-the 12.7 GB of inputs."""
+the 12.7 GB of inputs.
+
+The FP8 path (e4m3 slices with per-block scales, the operands config c5 names) is
+checked against its own bound, 8 x 2^-(5 NS - 1) relative to |E| and to the
+largest occupation number (tests/test_gpu_fp8.py derives it), which lies outside
+the 1e-6 Eh contract of the mixed paths: at |E| ~ 7e7 Eh it allows ~1e3 Eh."""
 import json
 import os
 
@@ -27,16 +32,25 @@ pytestmark = pytest.mark.gpu
 HERE = os.path.dirname(os.path.abspath(__file__))
 
 
-def test_c5_full_size_against_golden():
+@pytest.fixture(scope="module")
+def c5_inputs():
     dp = need_gpu()
-    with open(os.path.join(HERE, "golden", "c5_s0.5.json")) as f:
-        gold = json.load(f)
-    tr = gold["truncation"][0]
-    occ_ref = np.array(gold["occ"])
     print("c5: drawing inputs", flush=True)
     inp = synth.config_inputs("c5")
     d = dp.upload_inputs(inp)
     del inp
+    yield d
+    del d
+    torch.cuda.empty_cache()
+
+
+def test_c5_full_size_against_golden(c5_inputs):
+    dp = need_gpu()
+    d = c5_inputs
+    with open(os.path.join(HERE, "golden", "c5_s0.5.json")) as f:
+        gold = json.load(f)
+    tr = gold["truncation"][0]
+    occ_ref = np.array(gold["occ"])
     for precision, tol, occ_tol, corr_precision in ((dp.FP64, 1e-8, 1e-11, dp.FP64),
                                                     (dp.BF16_SLICED, 1e-6, 1e-8, dp.INT8_SLICED),
                                                     (dp.INT8_SLICED, 1e-6, 1e-8, dp.INT8_SLICED)):
@@ -62,3 +76,26 @@ def test_c5_full_size_against_golden():
         assert np.abs(occ - occ_ref).max() <= occ_tol * occ_ref.max()
         del r, t, c
         torch.cuda.empty_cache()
+
+
+def test_c5_fp8_within_its_bound(c5_inputs):
+    dp = need_gpu()
+    d = c5_inputs
+    with open(os.path.join(HERE, "golden", "c5_s0.5.json")) as f:
+        gold = json.load(f)
+    tr = gold["truncation"][0]
+    occ_ref = np.array(gold["occ"])
+    bound = 8.0 * 2.0 ** -(5 * 4 - 1)
+    print("c5: precision FP8", flush=True)
+    opts = dp.make_opts(120, 12, 2000, 6000, 0.5, precision=dp.FP8_SLICED)
+    r = dp.build_vv_density(opts, d["eps_hole"], d["eps_vir"], d["gamma_act"], d["B"])
+    e = r["e_pt2"].cpu().numpy()
+    E = sum(gold["energy"])
+    dE = dd_diff((float(e[0]), float(e[1])), gold["energy"])
+    t = dp.fno_truncate(r["D_vv"], tr["p_o"])
+    occ = t["occ"].cpu().numpy()
+    dON = np.abs(occ - occ_ref).max()
+    print(f"  dE {dE:.3e} Eh (rel {dE / abs(E):.2e}, bound {bound:.2e}), max dON {dON:.3e} "
+          f"(rel {dON / occ_ref.max():.2e}), kept {t['n_kept']} (oracle {tr['n_kept']})", flush=True)
+    assert dE <= bound * abs(E)
+    assert dON <= bound * occ_ref.max()
