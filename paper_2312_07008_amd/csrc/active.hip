@@ -6,7 +6,8 @@
 // (the same for the renormalized integrals), and
 //     D += 1/2 sum_{kl} n~_k n~_l T'_kl (2T'_kl - T'_kl^T)^T,
 //     E += 1/4 sum_{kl} n~_k n~_l <Vr'_kl, 2T'_kl - T'_kl^T>,   n~ = (2,...,2, n_1..n_act).
-// The rotations are FP64 GEMMs over stacked amplitude matrices (see api.cpp);
+// The core-active rotations stream the stacked matrices through rotate_stack_kernel
+// (n_act <= 32), the active-active one (K = n_act^2) is an FP64 GEMM (api.cpp);
 // this file holds the small kernels around them.
 #include "common.h"
 #include "kernels.h"
@@ -26,6 +27,74 @@ __global__ void kron_uu_kernel(const double* U, int na, double* W) {
 hipError_t launch_kron_uu(const double* U, int na, double* W, hipStream_t st) {
   const int n2 = na * na;
   hipLaunchKernelGGL(kron_uu_kernel, dim3((n2 + 127) / 128, n2), dim3(128), 0, st, U, na, W);
+  return hipGetLastError();
+}
+
+// Rotation of stacked n_v x n_v matrices to the natural active basis, for the
+// core-active pairs: out[b][k][e] = sum_u U[u][k] in[b][u][e], e < n = n_v^2, one
+// stack of na matrices per batch entry b.  Thread = two consecutive elements e of
+// every matrix of its stack: it reads the na inputs once (16-byte loads,
+// consecutive threads on consecutive addresses) and writes the na outputs once,
+// so the kernel streams each stack through HBM once; U (na <= NAMAX) sits in LDS
+// and every wave reads the same entry at a time (a broadcast).  As a GEMM of
+// shape (na x na) x (na x n) on 128-row tiles it ran at under 1 TB/s.
+template <int NAMAX, bool VEC>
+__global__ __launch_bounds__(256) void rotate_stack_kernel(const double* U, int na, const double* in, double* out,
+                                                           long long n) {
+  __shared__ double su[NAMAX * NAMAX];
+  for (int i = threadIdx.x; i < na * na; i += 256) su[i] = U[i];
+  __syncthreads();
+  const long long e = 2 * ((long long)blockIdx.x * 256 + threadIdx.x);
+  if (e >= n) return;
+  const size_t bo = (size_t)blockIdx.y * na * n;
+  const bool two = VEC || e + 1 < n;  // VEC: n even, so both elements exist
+  double2 x[NAMAX];
+#pragma unroll
+  for (int u = 0; u < NAMAX; ++u) {
+    x[u] = make_double2(0.0, 0.0);
+    if (u < na) {
+      const double* src = in + bo + (size_t)u * n + e;
+      if (VEC) x[u] = *reinterpret_cast<const double2*>(src);
+      else x[u] = make_double2(src[0], two ? src[1] : 0.0);
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < NAMAX; ++k) {
+    if (k >= na) break;
+    double2 acc = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int u = 0; u < NAMAX; ++u) {
+      if (u < na) {
+        const double c = su[u * na + k];
+        acc.x = fma(c, x[u].x, acc.x);
+        acc.y = fma(c, x[u].y, acc.y);
+      }
+    }
+    double* dst = out + bo + (size_t)k * n + e;
+    if (VEC) {
+      *reinterpret_cast<double2*>(dst) = acc;
+    } else {
+      dst[0] = acc.x;
+      if (two) dst[1] = acc.y;
+    }
+  }
+}
+
+hipError_t launch_rotate_stack(const double* U, int na, const double* in, double* out, long long n, int batch,
+                               hipStream_t st) {
+  if (na <= 0 || n <= 0 || batch <= 0) return hipSuccess;
+  if (na > 32 || batch > 65535) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)((n + 511) / 512), batch), block(256);
+  const bool vec = (n % 2) == 0;
+#define ROT(NA_)                                                                                         \
+  do {                                                                                                   \
+    if (vec) hipLaunchKernelGGL((rotate_stack_kernel<NA_, true>), grid, block, 0, st, U, na, in, out, n);  \
+    else hipLaunchKernelGGL((rotate_stack_kernel<NA_, false>), grid, block, 0, st, U, na, in, out, n);     \
+  } while (0)
+  if (na <= 8) ROT(8);
+  else if (na <= 16) ROT(16);
+  else ROT(32);
+#undef ROT
   return hipGetLastError();
 }
 

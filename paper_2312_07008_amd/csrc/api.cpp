@@ -517,12 +517,17 @@ static int run_active_blocks(const PassPlan& pl, const dfpt2_opts& o, const doub
       return hip_fail(e, "pair reduce");
     if ((e = launch_scatter_active_pair_info(pairs, tn2, np, pl.n_h, pair_energy, pair_tnorm, s)) != hipSuccess)
       return hip_fail(e, "scatter");
-    if ((e = gemm_f64(Ua, na, 0, 1, Tin, (int)mat, mat * na, 0, Tout, (int)mat, mat * na, na, (int)mat, na, nc, 1.0,
-                      0.0, s)) != hipSuccess)
-      return hip_fail(e, "rotate T");
-    if ((e = gemm_f64(Ua, na, 0, 1, Vin, (int)mat, mat * na, 0, Vout, (int)mat, mat * na, na, (int)mat, na, nc, 1.0,
-                      0.0, s)) != hipSuccess)
-      return hip_fail(e, "rotate V");
+    if (na <= 32) {  // streamed: each stack through HBM once
+      if ((e = launch_rotate_stack(Ua, na, Tin, Tout, mat, nc, s)) != hipSuccess) return hip_fail(e, "rotate T");
+      if ((e = launch_rotate_stack(Ua, na, Vin, Vout, mat, nc, s)) != hipSuccess) return hip_fail(e, "rotate V");
+    } else {
+      if ((e = gemm_f64(Ua, na, 0, 1, Tin, (int)mat, mat * na, 0, Tout, (int)mat, mat * na, na, (int)mat, na, nc, 1.0,
+                        0.0, s)) != hipSuccess)
+        return hip_fail(e, "rotate T");
+      if ((e = gemm_f64(Ua, na, 0, 1, Vin, (int)mat, mat * na, 0, Vout, (int)mat, mat * na, na, (int)mat, na, nc, 1.0,
+                        0.0, s)) != hipSuccess)
+        return hip_fail(e, "rotate V");
+    }
     if ((e = launch_active_weights(0, np, pl.n_core, na, pairs, occ, scale_d, wd, we, s)) != hipSuccess)
       return hip_fail(e, "weights");
     if ((e = launch_rotated_energy(Tout, Vout, slots, np, nv, epart, s)) != hipSuccess)

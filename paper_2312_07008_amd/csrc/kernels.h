@@ -154,6 +154,10 @@ hipError_t launch_energy_finalize(const double* pe, const double* tn2, const int
 
 // ------------------------------------------------------------ active holes
 hipError_t launch_kron_uu(const double* U, int na, double* W, hipStream_t st);
+// out[b][k][e] = sum_u U[u][k] in[b][u][e] for e < n, k, u < na, b < batch
+// (stacks of na matrices of n elements; na <= 32)
+hipError_t launch_rotate_stack(const double* U, int na, const double* in, double* out, long long n, int batch,
+                               hipStream_t st);
 hipError_t launch_build_active_pairs(int kind, int m0, int ncore, int n_core, int na, int2* pairs, int* slots,
                                      hipStream_t st);
 hipError_t launch_active_weights(int kind, int n, int n_core, int na, const int2* pairs, const double* occ,
