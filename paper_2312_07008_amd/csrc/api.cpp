@@ -115,16 +115,19 @@ int plan_pass(const dfpt2_opts* o, PassPlan* pl, bool energy_only) {
     return fail(DFPT2_ERR_INVALID_ARG, "n_vir too large for exact INT8 density sums with %d digits", p.ns2);
   if (energy_only) p.ns2 = 1;
   // sliced density: splits of the pair range chosen so that workgroup tiles x splits
-  // fill whole rounds of two workgroups per CU on 256 CUs
+  // fill whole rounds on 256 CUs (one BF16 workgroup per CU, two INT8 ones), with
+  // at least four rounds and the batch's pairs dealt evenly to the splits
   p.nsplit2 = 1;
   if (p.ns2 >= 2) {
     double best = 1e30;
     const int cap = p.batch < 64 ? p.batch : 64;
     const int tiles = p.precision == DFPT2_BF16_SLICED ? p.nTD : p.nTP;
+    const double slots = p.precision == DFPT2_BF16_SLICED ? 256.0 : 512.0;
     for (int k = 1; k <= cap; ++k) {
       const double w = (double)tiles * k;
-      const double rounds = std::ceil(w / 512.0);
-      const double waste = (rounds * 512.0 - w) / w + (w < 2048.0 ? 1.0 : 0.0);
+      const double rounds = std::ceil(w / slots);
+      const double per = (double)p.batch / k;
+      const double waste = (rounds * slots - w) / w + (std::ceil(per) - per) / per + (w < 4.0 * slots ? 1.0 : 0.0);
       if (waste < best - 1e-12) {
         best = waste;
         p.nsplit2 = k;

@@ -2,53 +2,57 @@
 // (Eq. A9 with zero cumulants) accumulated over hole pairs from BF16 slices of
 // the amplitudes, on the 32x32x16 BF16 MFMA.
 //
-// Per unordered pair the contribution is X1 Y1^T + X2 Y2^T (split_t.hip gives
-// the slices of the rows of X1 = T, X2 = T^T, Y1 = 2T - T^T, Y2 = 2T^T - T).
-// As in the pair kernel, the slice products of level s + t - 1 <= NS are kept.
-// The operands carry one exponent per (row, 64-column block), so within one
-// block of one product of one pair every product of a row a of X and a row b of
-// Y is an integer multiple of one unit (the two rows' block scales): the level-1
-// and level-2 sums are exact in FP32 over the block's 64 contraction steps and
-// are added into FP64 at the end of every block (with the pair's weight);
-// levels >= 3 are summed in FP32 per product.  The two products carry different
-// units, so the contraction runs over X1 / Y1 first and X2 / Y2 after it, with
-// one set of accumulators.  D is symmetric: only
-// tiles on or above the diagonal are formed.  Diagonal elements are left out:
-// split_t.hip sums them exactly in FP64 (the rows of X and Y there carry the
-// same amplitudes, so the dropped slice products would not average out).
+// Per unordered pair the contribution is X1 Y1^T + X2 Y2^T (the slices of the
+// rows of X1 = T, X2 = T^T, Y1 = 2T - T^T, Y2 = 2T^T - T come from
+// epi_split_bf16.hip or split_t.hip).  As in the pair kernel, the slice products
+// of level s + t - 1 <= NS are kept.  The operands carry one exponent per (row,
+// 64-column block), so within one block of one product of one pair every
+// product of a row a of X and a row b of Y is an integer multiple of one unit
+// (the two rows' block scales): the level-1 and level-2 sums are exact in FP32
+// over the block's 64 contraction steps and are added into FP64 at the end of
+// every block (with the pair's weight); levels >= 3 are summed in FP32 per
+// product.  The two products carry different units, so the contraction runs over
+// X1 / Y1 first and X2 / Y2 after it, with one set of accumulators.  D is
+// symmetric: only tiles on or above the diagonal are formed, and of a tile on
+// the diagonal only the elements above it are written.  Diagonal elements are
+// left out: the amplitude split sums them exactly in FP64 (the rows of X and Y
+// there carry the same amplitudes, so the dropped slice products would not
+// average out).
 //
-// Workgroup = (128 x 64 tile (I, J) of D with J >= 2I in 64-wide units, split s):
-// split s owns a contiguous range of pairs and accumulates into its own slice
-// Dpart[s]; the slices are summed in a fixed order afterwards
-// (density_reduce_kernel), so results are bitwise reproducible.  A 128 x 64
-// tile moves 192 rows per contraction chunk for 8192 outputs (a 64 x 64 tile
-// pair of both products at once: 256 rows for 8192), 25% fewer bytes per flop.
-// Four waves, wave (wr, wc) owns rows 64 wr .. + 63 (two 32 x 32 MFMA blocks)
-// and columns 32 wc .. + 31; on a diagonal tile (J = 2I) rows 64 .. 127 lie
-// below the diagonal and their two waves only help with the loads.  Rows of X
-// beyond n_v_pad (the last row tile when n_v_pad / 64 is odd) are loaded only
-// there: the operand matrices are rows_pad rows apart, and those rows are never
-// written or used.  Staging as in pair_bf16_v.hip: 16-wide chunks of the 128-row
-// X panel and the 64-row Y panel go from global memory straight into LDS
-// (XOR-swizzled 128-byte rows), double buffered, 24 KB per buffer, two
-// workgroups per CU; each step issues the next chunk's loads before its fragment
-// reads and waits for them before its closing barrier.  The 1-D launch is
-// remapped so that every XCD walks a contiguous range of (split, tile):
-// workgroups resident on one XCD read the same pairs' slices.
+// Workgroup = (128 x 128 tile (I, J) of D, I <= J, split s): split s owns a
+// contiguous range of pairs and accumulates into its own slice Dpart[s]; the
+// slices are summed in a fixed order afterwards (density_reduce_kernel), so
+// results are bitwise reproducible.  Eight waves, one workgroup per CU, as the
+// pair product kernel (pair_bf16_v.hip): wave (wr, wc) owns rows 64 wr .. + 63
+// (two 32 x 32 MFMA blocks) and columns 32 wc .. + 31; on a diagonal tile the
+// two waves wholly below the diagonal only help with the loads.  A 128 x 128
+// tile moves 256 rows per contraction chunk for 16384 outputs, a third fewer
+// bytes per output than 128 x 64 tiles (192 rows for 8192).  Rows beyond n_v_pad
+// (the last tile row when n_v_pad / 64 is odd) are loaded only there: the
+// operand matrices are rows_pad rows apart, and the outputs those rows feed are
+// never written.  Staging as in the pair kernel: 16-wide chunks of the two
+// 128-row panels go from global memory straight into LDS (XOR-swizzled 128-byte
+// rows) through a ring of four 32 KB slots; step c issues the loads of chunk
+// c + 3, runs the products of chunk c, waits for its own loads of chunk c + 1
+// only and closes with a barrier that carries no memory fence.  Exponent blocks
+// (four chunks) line up with the ring's revolutions, so the flushes sit at fixed
+// steps.  The 1-D launch is remapped so that every XCD walks a contiguous range
+// of (split, tile): workgroups resident on one XCD read the same pairs' slices.
+#include <type_traits>
+
 #include "common.h"
 #include "kernels.h"
 
 namespace dfpt2 {
 
 namespace {
-constexpr int TX = 128;  // rows of D per tile (X panel)
-constexpr int TY = 64;   // columns of D per tile (Y panel)
+constexpr int TD = 128;  // tile edge
 constexpr int KC = 16;
 constexpr int SLOTS = 8;
-constexpr int KB_X = TX / 8, KB_Y = TY / 8;  // kilobytes of the two panels per chunk
-constexpr int KB_W = (KB_X + KB_Y) / 4;      // kilobytes per wave per chunk
-constexpr int PY = KB_X * 64;                // u4 offset of the Y panel in a buffer
-constexpr int FLUSH_CHUNKS = 64 / KC;  // one exponent block of the operands
+constexpr int NBUF = 4;                  // ring slots
+constexpr int KB_P = TD / 8;             // kilobytes of one panel per chunk
+constexpr int KB_W = 2 * KB_P / 8;       // kilobytes per wave per chunk
+constexpr int BLK_CHUNKS = 64 / KC;      // chunks per exponent block of the operands
 typedef uint32_t u4 __attribute__((ext_vector_type(4)));
 typedef __attribute__((address_space(3))) void lds_void;
 typedef __attribute__((address_space(1))) void gbl_void;
@@ -60,40 +64,48 @@ __device__ inline int xcd_block_d(int h, int nblk) {
   return (x < rem) ? x * (q + 1) + k : rem * (q + 1) + (x - rem) * q + k;
 }
 
-// tile td of the row-major list of (I, J), J = 2I .. nt - 1
-__device__ inline void density_tile(int td, int nt, int& I, int& J) {
-  int i = 0, rem = td;
-  while (rem >= nt - 2 * i) {
-    rem -= nt - 2 * i;
-    ++i;
-  }
-  I = i;
-  J = 2 * i + rem;
-}
+// s_waitcnt immediate (gfx9 encoding): wait until at most n vector-memory
+// operations of this wave are outstanding, other counters untouched
+constexpr int vm_wait_imm(int n) { return (n & 15) | (((n >> 4) & 3) << 14) | (7 << 4) | (15 << 8); }
 }  // namespace
 
 template <int NS>
-__global__ __launch_bounds__(256, 2) void density_bf16_kernel(DensitySlicedArgs a) {
+__global__ __launch_bounds__(512, 1) void density_bf16_kernel(DensitySlicedArgs a) {
   static_assert(2 * NS <= SLOTS, "slices per LDS row");
-  static_assert(KB_W * 4 == KB_X + KB_Y, "whole kilobytes per wave");
-  __shared__ u4 lds0[(KB_X + KB_Y) * 64];
-  __shared__ u4 lds1[(KB_X + KB_Y) * 64];
+  static_assert(NBUF == BLK_CHUNKS, "a ring revolution is one exponent block");
+  // distinct arrays per ring slot and panel, so that the compiler's alias scopes
+  // tell the slots apart (a read of one slot does not wait for loads into another)
+  __shared__ u4 lx0[KB_P * 64], lx1[KB_P * 64], lx2[KB_P * 64], lx3[KB_P * 64];
+  __shared__ u4 ly0[KB_P * 64], ly1[KB_P * 64], ly2[KB_P * 64], ly3[KB_P * 64];
+  auto slot_x = [&](auto K) __attribute__((always_inline)) -> u4* {
+    if constexpr (K() == 0) return lx0;
+    else if constexpr (K() == 1) return lx1;
+    else if constexpr (K() == 2) return lx2;
+    else return lx3;
+  };
+  auto slot_y = [&](auto K) __attribute__((always_inline)) -> u4* {
+    if constexpr (K() == 0) return ly0;
+    else if constexpr (K() == 1) return ly1;
+    else if constexpr (K() == 2) return ly2;
+    else return ly3;
+  };
+  const int nt2 = (a.nt + 1) / 2;  // 128-row tiles
   const int L = xcd_block_d(blockIdx.x, a.nTP * a.nsplit);
   const int split = L / a.nTP, td = L - split * a.nTP;
   int I, J;
-  density_tile(td, a.nt, I, J);
+  tile_pair(td, nt2, I, J);
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int wr = w >> 1, wc = w & 1;
-  const bool below = (J == 2 * I) && wr == 1;  // wave-uniform
+  const int wr = w >> 2, wc = w & 3;
+  const bool idle = (I == J) && wr == 1 && wc < 2;  // wave-uniform: wholly below the diagonal
   const int n_v = a.n_v;
   const int p0 = (int)((long long)split * a.n_pairs / a.nsplit);  // balanced pair ranges
   const int p1 = (int)((long long)(split + 1) * a.n_pairs / a.nsplit);
-  const int ncc = a.n_v_pad / KC;  // chunks per product
-  const int per_pair = 2 * ncc;
-  const int total = (p1 > p0) ? (p1 - p0) * per_pair : 0;
+  const int nblk = a.nt;              // 64-column exponent blocks per product
+  const int ncc = BLK_CHUNKS * nblk;  // chunks per product
+  const int total = (p1 > p0) ? (p1 - p0) * 2 * ncc : 0;  // a multiple of 8
 
-  // kilobyte kb < KB_X of a chunk is rows 8 kb .. + 7 of the X panel (rows of
-  // tile I), kilobyte KB_X + kb rows 8 kb .. + 7 of the Y panel (rows of tile J);
+  // kilobyte kb < KB_P of a chunk is rows 8 kb .. + 7 of the X panel (rows of
+  // tile I), kilobyte KB_P + kb rows 8 kb .. + 7 of the Y panel (rows of tile J);
   // wave w moves kilobytes KB_W w .. + KB_W - 1; lane l fills physical slot l % 8
   // of row l / 8
   const int q_w = __builtin_amdgcn_readfirstlane(w);
@@ -101,24 +113,31 @@ __global__ __launch_bounds__(256, 2) void density_bf16_kernel(DensitySlicedArgs 
   const size_t mat_bytes = (size_t)a.rows_pad * row_bytes;
   const char* Ts = reinterpret_cast<const char*>(a.Ts);
   const int l3 = lane >> 3, l7 = lane & 7;
-  auto src_off = [&](int kb) -> uint32_t {  // kb within its panel
+  auto src_off = [&](int kb) __attribute__((always_inline)) -> uint32_t {  // kb within its panel
     const int row = 8 * kb + l3;
     const int sl = l7 ^ swz8(row);
     const int t = sl >> 1, h = sl & 1;
     return (uint32_t)(row * row_bytes + (t < NS ? t * 32 + h * 16 : 0));
   };
-  // step idx: pair p0 + idx / per_pair, product h (0: X1 Y1^T, 1: X2 Y2^T), chunk ch
-  auto load_chunk = [&](int idx, u4* buf) {
-    const int pi = idx / per_pair, rem = idx - pi * per_pair;
-    const int h = rem >= ncc ? 1 : 0, ch = rem - h * ncc;
-    const char* pb = Ts + (size_t)(p0 + pi) * 4 * mat_bytes + (size_t)ch * (KC * NS * 2);
-    const char* pX = pb + (size_t)h * mat_bytes + (size_t)I * TX * row_bytes;
-    const char* pY = pb + (size_t)(2 + h) * mat_bytes + (size_t)J * TY * row_bytes;
+  // load cursor: pair lq, product lh (0: X1 Y1^T, 1: X2 Y2^T), chunk lch
+  int lq = p0, lh = 0, lch = 0;
+  auto load_next = [&](auto K) __attribute__((always_inline)) {  // chunk at the cursor into slot K; cursor moves on
+    const char* pb = Ts + (size_t)lq * 4 * mat_bytes + (size_t)lch * (KC * NS * 2);
+    const char* pX = pb + (size_t)lh * mat_bytes + (size_t)I * TD * row_bytes;
+    const char* pY = pb + (size_t)(2 + lh) * mat_bytes + (size_t)J * TD * row_bytes;
 #pragma unroll
     for (int m = 0; m < KB_W; ++m) {
       const int kb = KB_W * q_w + m;  // wave-uniform
-      const char* src = kb < KB_X ? pX + src_off(kb) : pY + src_off(kb - KB_X);
-      __builtin_amdgcn_global_load_lds((gbl_void*)src, (lds_void*)(buf + kb * 64), 16, 0, 0);
+      if (kb < KB_P)
+        __builtin_amdgcn_global_load_lds((gbl_void*)(pX + src_off(kb)), (lds_void*)(slot_x(K) + kb * 64), 16, 0, 0);
+      else
+        __builtin_amdgcn_global_load_lds((gbl_void*)(pY + src_off(kb - KB_P)),
+                                         (lds_void*)(slot_y(K) + (kb - KB_P) * 64), 16, 0, 0);
+    }
+    if (++lch == ncc) {
+      lch = 0;
+      lh ^= 1;
+      if (lh == 0) ++lq;
     }
   };
 
@@ -135,18 +154,36 @@ __global__ __launch_bounds__(256, 2) void density_bf16_kernel(DensitySlicedArgs 
   }
 
   const int r32 = lane & 31, hq = lane >> 5;
-  const int rowY = wc * 32 + r32, fY = swz8(rowY);
-  auto compute = [&](const u4* buf) {
-    if (below) return;
-    bf8v fb[NS];
+  // per-lane u4 index of every fragment within a slot; passed through an empty asm
+  // in every step, so that the compiler forms each slot's addresses at the read
+  int offY[NS], offX[2][NS];
+  {
+    const int rowY = wc * 32 + r32, fY = swz8(rowY);
 #pragma unroll
-    for (int s = 0; s < NS; ++s) fb[s] = __builtin_bit_cast(bf8v, buf[PY + rowY * SLOTS + ((2 * s + hq) ^ fY)]);
+    for (int s = 0; s < NS; ++s) offY[s] = rowY * SLOTS + ((2 * s + hq) ^ fY);
 #pragma unroll
     for (int b = 0; b < 2; ++b) {
       const int rowX = wr * 64 + b * 32 + r32, fX = swz8(rowX);
+#pragma unroll
+      for (int s = 0; s < NS; ++s) offX[b][s] = rowX * SLOTS + ((2 * s + hq) ^ fX);
+    }
+  }
+  auto compute = [&](auto K) __attribute__((always_inline)) {
+    if (idle) return;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      asm volatile("" : "+v"(offY[s]));
+      asm volatile("" : "+v"(offX[0][s]));
+      asm volatile("" : "+v"(offX[1][s]));
+    }
+    bf8v fb[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) fb[s] = __builtin_bit_cast(bf8v, slot_y(K)[offY[s]]);
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
       bf8v fa[NS];
 #pragma unroll
-      for (int s = 0; s < NS; ++s) fa[s] = __builtin_bit_cast(bf8v, buf[rowX * SLOTS + ((2 * s + hq) ^ fX)]);
+      for (int s = 0; s < NS; ++s) fa[s] = __builtin_bit_cast(bf8v, slot_x(K)[offX[b][s]]);
 #pragma unroll
       for (int s = 0; s < NS; ++s)
 #pragma unroll
@@ -156,9 +193,24 @@ __global__ __launch_bounds__(256, 2) void density_bf16_kernel(DensitySlicedArgs 
         }
     }
   };
-  // after chunk ch of the current product (weight wp)
-  auto flush = [&](int ch, bool prod_end, double wp) {
-    if ((ch + 1) % FLUSH_CHUNKS == 0 || prod_end) {
+  // pair weight: one ordered pair w, halved for i == j (both orders are the same);
+  // read through the constant address space, so the loads are scalar and never
+  // count among the vector loads the steps wait for
+  typedef __attribute__((address_space(4))) const int c_int;
+  typedef __attribute__((address_space(4))) const double c_double;
+  auto weight = [&](int p) __attribute__((always_inline)) {
+    const c_int* pr = (const c_int*)a.pairs + 2 * (size_t)p;
+    double wp = a.w * (pr[0] == pr[1] ? 0.5 : 1.0);
+    if (a.pw) wp *= ((const c_double*)a.pw)[p];
+    return wp;
+  };
+  // compute cursor: pair cq, product chalf, exponent block cblk of the chunks being computed
+  int cq = p0, chalf = 0, cblk = 0;
+  double wp = (total > 0) ? weight(p0) : 0.0;
+  // after the last chunk of an exponent block: the exact level-1 and level-2 sums
+  // go into FP64; at the end of a product also level 3+, and the cursor moves on
+  auto end_block = [&]() __attribute__((always_inline)) {
+    if (!idle) {
 #pragma unroll
       for (int b = 0; b < 2; ++b)
 #pragma unroll
@@ -168,66 +220,89 @@ __global__ __launch_bounds__(256, 2) void density_bf16_kernel(DensitySlicedArgs 
           acc[b][1][r] = 0.f;
         }
     }
-    if (prod_end) {
+    if (++cblk == nblk) {  // uniform
+      cblk = 0;
+      if (!idle) {
 #pragma unroll
-      for (int b = 0; b < 2; ++b)
+        for (int b = 0; b < 2; ++b)
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          dD[b][r] += wp * (double)acc[b][2][r];
-          acc[b][2][r] = 0.f;
-        }
-    }
-  };
-  // pair weight: one ordered pair w, halved for i == j (both orders are the same)
-  auto weight = [&](int p) {
-    const int2 pr = a.pairs[p];
-    double wp = a.w * (pr.x == pr.y ? 0.5 : 1.0);
-    if (a.pw) wp *= a.pw[p];
-    return wp;
-  };
-  int cp = p0, cch = 0, half = 0;  // pair, chunk and product of the step being computed
-  double wp = (total > 0) ? weight(p0) : 0.0;
-  // step idx: the loads of step idx + 1 go out first and overlap the products of
-  // step idx; all have landed at the closing barrier (buffers swapped through
-  // pointers, as in pair_bf16_v.hip)
-  auto step = [&](int idx, u4* cur, u4* nxt) {
-    if (idx + 1 < total) load_chunk(idx + 1, nxt);
-    compute(cur);
-    const bool prod_end = (cch + 1 == ncc);
-    flush(cch, prod_end, wp);
-    if (prod_end) {
-      cch = 0;
-      if (half) {
-        half = 0;
-        ++cp;
-        if (cp < p1) wp = weight(cp);
-      } else {
-        half = 1;
+          for (int r = 0; r < 16; ++r) {
+            dD[b][r] += wp * (double)acc[b][2][r];
+            acc[b][2][r] = 0.f;
+          }
       }
-    } else {
-      ++cch;
+      chalf ^= 1;
+      if (chalf == 0) {
+        ++cq;
+        if (cq < p1) wp = weight(cq);
+      }
     }
-    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-    __syncthreads();
+  };
+  // the workgroup barrier without the memory fence of __syncthreads (whose
+  // release waits for every outstanding load); the empty asm keeps the compiler
+  // from moving memory accesses across it
+  auto barrier = []() __attribute__((always_inline)) {
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+  };
+  // step of chunk c (slot K): the loads of chunk c + 3 go into slot KL, which
+  // chunk c - 1 was read from (every wave finished those reads before the last
+  // barrier); the products of chunk c follow (and the flush at the end of an
+  // exponent block); then each wave waits for its own loads of chunk c + 1 -- the
+  // loads of chunks c + 2 and c + 3 may stay in flight -- and the barrier makes
+  // every wave's part of chunk c + 1 visible.  The steady-state steps have no
+  // branch around a load or a wait; the last steps run as tail steps that check
+  // each load and wait for everything.
+  auto step = [&](int, auto K, auto KL, auto E) __attribute__((always_inline)) {
+    load_next(KL);
+    compute(K);
+    if constexpr (E()) end_block();
+    __builtin_amdgcn_s_waitcnt(vm_wait_imm(KB_W * (NBUF - 2)));
+    barrier();
+  };
+  auto tail_step = [&](int c, auto K, auto KL, auto E) __attribute__((always_inline)) {
+    if (c >= total) return;  // uniform
+    if (c + NBUF - 1 < total) load_next(KL);
+    compute(K);
+    if constexpr (E()) end_block();
+    __builtin_amdgcn_s_waitcnt(vm_wait_imm(0));
+    barrier();
+  };
+  using S0 = std::integral_constant<int, 0>;
+  using S1 = std::integral_constant<int, 1>;
+  using S2 = std::integral_constant<int, 2>;
+  using S3 = std::integral_constant<int, 3>;
+  using F = std::false_type;
+  using T = std::true_type;
+  // 4 steps from chunk c (c a multiple of 4): slot c % 4, one exponent block
+  auto ring = [&](int c, auto&& f) __attribute__((always_inline)) {
+    f(c, S0{}, S3{}, F{});
+    f(c + 1, S1{}, S0{}, F{});
+    f(c + 2, S2{}, S1{}, F{});
+    f(c + 3, S3{}, S2{}, T{});
   };
 
   if (total > 0) {
-    load_chunk(0, lds0);
-    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-    __syncthreads();
-    u4 *cur = lds0, *nxt = lds1;  // steps idx, idx + 1
-    for (int idx = 0; idx < total; ++idx) {
-      step(idx, cur, nxt);
-      u4* t = cur;
-      cur = nxt;
-      nxt = t;
-    }
+    // chunks 0 .. 2 into slots 0 .. 2
+    load_next(S0{});
+    load_next(S1{});
+    load_next(S2{});
+    __builtin_amdgcn_s_waitcnt(vm_wait_imm(KB_W * (NBUF - 2)));  // chunk 0 has landed
+    barrier();
+    int c = 0;
+    // steady state: every step loads a chunk that exists (up to chunk c + 6)
+    for (; c + 2 * NBUF - 2 < total; c += NBUF) ring(c, step);
+    ring(c, tail_step);
+    if (c + NBUF < total) ring(c + NBUF, tail_step);
   }
 
-  // D tile (32x32 layout: register r of lane l is row 8(r/4) + 4(l/32) + r%4, column l%32)
-  if (below) return;
+  // D tile (32x32 layout: register r of lane l is row 8(r/4) + 4(l/32) + r%4, column
+  // l%32); only elements above the diagonal are written (the reduction reads that
+  // triangle; the diagonal comes from the exact FP64 sum of the amplitude split)
+  if (idle) return;
   double* Dp = a.Dpart + (size_t)split * n_v * n_v;
-  const int gb = J * TY + wc * 32 + r32;
+  const int gb = J * TD + wc * 32 + r32;
   if (gb < n_v) {
     // all reads of the old tile first (rows beyond n_v read row n_v - 1 and are
     // not written back), so that they are in flight together
@@ -236,7 +311,7 @@ __global__ __launch_bounds__(256, 2) void density_bf16_kernel(DensitySlicedArgs 
       for (int b = 0; b < 2; ++b)
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
-          const int ga = I * TX + wr * 64 + b * 32 + 8 * (r >> 2) + 4 * hq + (r & 3);
+          const int ga = I * TD + wr * 64 + b * 32 + 8 * (r >> 2) + 4 * hq + (r & 3);
           dD[b][r] += Dp[(size_t)min(ga, n_v - 1) * n_v + gb];
         }
     }
@@ -244,26 +319,24 @@ __global__ __launch_bounds__(256, 2) void density_bf16_kernel(DensitySlicedArgs 
     for (int b = 0; b < 2; ++b)
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
-        const int ga = I * TX + wr * 64 + b * 32 + 8 * (r >> 2) + 4 * hq + (r & 3);
-        // the diagonal comes from the exact FP64 sum of the amplitude split
-        if (ga < n_v && ga != gb) Dp[(size_t)ga * n_v + gb] = dD[b][r];
+        const int ga = I * TD + wr * 64 + b * 32 + 8 * (r >> 2) + 4 * hq + (r & 3);
+        if (ga < gb) Dp[(size_t)ga * n_v + gb] = dD[b][r];
       }
   }
 }
 
 int density_bf16_tiles(int nt) {
-  int n = 0;
-  for (int i = 0; 2 * i < nt; ++i) n += nt - 2 * i;
-  return n;
+  const int nt2 = (nt + 1) / 2;
+  return nt2 * (nt2 + 1) / 2;
 }
 
 hipError_t launch_density_bf16(const DensitySlicedArgs& a, int ns, hipStream_t st) {
   if (a.n_pairs <= 0) return hipSuccess;
-  // the X panels of the last row tile reach row 128 ceil(nt / 2) - 1
-  if (a.n_v_pad != 64 * a.nt || a.rows_pad % TX != 0 || a.rows_pad < TX * ((a.nt + 1) / 2) ||
+  // the panels of the last tile reach row 128 ceil(nt / 2) - 1
+  if (a.n_v_pad != 64 * a.nt || a.rows_pad % TD != 0 || a.rows_pad < TD * ((a.nt + 1) / 2) ||
       a.nTP != density_bf16_tiles(a.nt) || (long long)a.nTP * a.nsplit > 0x7fffffffLL)
     return hipErrorInvalidValue;
-  dim3 grid(a.nTP * a.nsplit), block(256);
+  dim3 grid(a.nTP * a.nsplit), block(512);
   switch (ns) {
     case 2: hipLaunchKernelGGL(density_bf16_kernel<2>, grid, block, 0, st, a); break;
     case 3: hipLaunchKernelGGL(density_bf16_kernel<3>, grid, block, 0, st, a); break;
