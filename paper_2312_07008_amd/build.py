@@ -35,6 +35,7 @@ SOURCES = [
     "pair_bf16_v.hip",
     "pair_fp8.hip",
     "pair_i8.hip",
+    "pair_i8_v.hip",
     "split_t.hip",
     "epi_split_bf16.hip",
     "density_bf16.hip",

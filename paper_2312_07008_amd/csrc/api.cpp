@@ -67,8 +67,10 @@ int plan_pass(const dfpt2_opts* o, PassPlan* pl, bool energy_only) {
   const size_t mat = (size_t)p.n_v * p.n_v;
   int64_t batch = o->pair_batch;
   // energy-only passes store no amplitudes: one batch of every pair, except with
-  // BF16 slices, whose product writes V to a buffer of one batch for the epilogue
-  const bool v_buffer = energy_only && o->precision == DFPT2_BF16_SLICED;
+  // BF16 slices or INT8 digits, whose product writes V to a buffer of one batch
+  // for the epilogue kernel
+  const bool v_buffer =
+      energy_only && (o->precision == DFPT2_BF16_SLICED || o->precision == DFPT2_INT8_SLICED);
   if (energy_only && !v_buffer) batch = 65535;
   if (batch == 0) {
     const double cap_bytes = 8.0e9;
@@ -91,8 +93,10 @@ int plan_pass(const dfpt2_opts* o, PassPlan* pl, bool energy_only) {
   p.ns1 = o->slices_gemm1 ? o->slices_gemm1 : default_slices_gemm1(o->precision);
   p.n_v_pad_d = (p.n_v + 63) / 64 * 64;
   // slab rows of the sliced operands and rows of the density operands: 128-multiples
-  // for BF16 (the 128-row tiles of the V kernel and of the density kernel)
-  p.n_v_pad = p.precision == DFPT2_BF16_SLICED ? (p.n_v + 127) / 128 * 128 : p.n_v_pad_d;
+  // for BF16 and INT8 digits (the 128-row tiles of the product kernels) and for the
+  // BF16 density kernel
+  p.n_v_pad = (p.precision == DFPT2_BF16_SLICED || p.precision == DFPT2_INT8_SLICED) ? (p.n_v + 127) / 128 * 128
+                                                                                      : p.n_v_pad_d;
   p.n_v_rows_t = p.precision == DFPT2_BF16_SLICED ? (p.n_v + 127) / 128 * 128 : p.n_v_pad_d;
   p.nTD = density_bf16_tiles(p.nt);
   p.nTP1 = p.nTP;
@@ -144,7 +148,7 @@ int plan_pass(const dfpt2_opts* o, PassPlan* pl, bool energy_only) {
   };
   p.off_pairs = take(sizeof(int2) * (size_t)(p.n_up > 0 ? p.n_up : 1));
   p.off_count = take(sizeof(int) * 4);
-  p.off_T = take(energy_only && !v_buffer ? 0 : sizeof(double) * mat * p.batch);  // T, or V of energy-only BF16
+  p.off_T = take(energy_only && !v_buffer ? 0 : sizeof(double) * mat * p.batch);  // T, or V of an energy-only pass
   p.off_epart = take(sizeof(double) * (size_t)p.batch * p.nTP1);
   p.off_tpart = take(sizeof(double) * (size_t)p.batch * p.nTP1);
   p.off_pe = take(sizeof(double) * 2 * (size_t)(p.n_up > 0 ? p.n_up : 1));
@@ -354,7 +358,18 @@ hipError_t launch_pair(const PairLaunch& L, const PairKernelArgs& a, int n_pairs
   b.s = a.s;
   b.e_weight = a.e_weight;
   if (L.precision == DFPT2_FP8_SLICED) return launch_pair_gemm_fp8(b, L.ns, n_pairs, st);
-  if (L.precision == DFPT2_INT8_SLICED) return launch_pair_gemm_i8(b, L.ns, n_pairs, st);
+  if (L.precision == DFPT2_INT8_SLICED) {  // the product on its own, then the epilogue kernel
+    const bool store = b.T || b.Vr;
+    if (!store) {
+      if (!L.vbuf) return launch_pair_gemm_i8(b, L.ns, n_pairs, st);  // energy only, fused
+      b.T = L.vbuf;
+    }
+    const hipError_t e = launch_pair_v_i8(b, L.ns, n_pairs, st);
+    if (e != hipSuccess) return e;
+    if (product) product->close();
+    ProfScope ps(DFPT2_STAGE_PAIR_EPILOGUE, st);
+    return launch_pair_epi_bf16(b, n_pairs, store, st);
+  }
   if (L.ts && b.T && !b.Vr) {  // split-BF16 density: V in b.T, then the epilogue that slices the amplitudes
     const hipError_t e = launch_pair_v_bf16(b, L.ns, n_pairs, st);
     if (e != hipSuccess) return e;
@@ -602,7 +617,8 @@ int run_pass(const PassPlan& pl, const dfpt2_opts& o, const double* eps_h, const
   const size_t mat = (size_t)pl.n_v * pl.n_v;
 
   PairLaunch L{pl.precision, pl.ns1, B, nullptr, nullptr, nullptr, pl.n_v_pad, pl.n_aux_pad, nullptr};
-  if (pl.energy_only && pl.precision == DFPT2_BF16_SLICED) L.vbuf = reinterpret_cast<double*>(ws + pl.off_T);
+  if (pl.energy_only && (pl.precision == DFPT2_BF16_SLICED || pl.precision == DFPT2_INT8_SLICED))
+    L.vbuf = reinterpret_cast<double*>(ws + pl.off_T);
   if (!pl.energy_only && pl.precision == DFPT2_BF16_SLICED && pl.ns2 >= 2) {
     L.ts = reinterpret_cast<__bf16*>(ws + pl.off_Ts);
     L.dgp = reinterpret_cast<double*>(ws + pl.off_dg);

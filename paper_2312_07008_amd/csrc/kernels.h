@@ -59,6 +59,9 @@ hipError_t launch_pair_epi_split_bf16(const PairSlicedArgs& a, int n_pairs, int 
                                       double* dgp, hipStream_t st);
 hipError_t launch_pair_gemm_fp8(const PairSlicedArgs& a, int ns, int n_pairs, hipStream_t st);
 hipError_t launch_pair_gemm_i8(const PairSlicedArgs& a, int ns, int n_pairs, hipStream_t st);
+// the INT8-digit product alone (pair_i8_v.hip): V into a.T (slabs of a multiple of
+// 128 rows), for pair_epi_bf16's epilogue
+hipError_t launch_pair_v_i8(const PairSlicedArgs& a, int ns, int n_pairs, hipStream_t st);
 // largest n_aux_pad for which the INT8 level sums stay exact with ns digits
 int pair_i8_max_aux_pad(int ns);
 // FP64 rows -> BF16 / FP8 slices, see split.hip.  BF16: rows whose largest

@@ -32,6 +32,7 @@
 // lane l of load m fills LDS unit 64 m + l and fetches whatever logical slot
 // lands there: the fetches of one load stay inside ~7 consecutive rows.
 #include "common.h"
+#include "i8_layout.h"
 #include "kernels.h"
 #include "pair_epilogue.h"
 
@@ -45,25 +46,6 @@ typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v16i __attribute__((ext_vector_type(16)));
 typedef __attribute__((address_space(3))) void lds_void;
 typedef __attribute__((address_space(1))) void gbl_void;
-
-template <int NS>
-__device__ inline int phys_slot(int r, int j) {
-  if constexpr (NS == 4) {
-    return j ^ ((r ^ (r >> 3)) & 7);
-  } else {
-    const int p = j + NS * (((r >> 2) ^ (r >> 3)) & 1);
-    return p >= 2 * NS ? p - 2 * NS : p;
-  }
-}
-template <int NS>
-__device__ inline int logical_slot(int r, int p) {
-  if constexpr (NS == 4) {
-    return p ^ ((r ^ (r >> 3)) & 7);
-  } else {
-    const int j = p - NS * (((r >> 2) ^ (r >> 3)) & 1);
-    return j < 0 ? j + 2 * NS : j;
-  }
-}
 
 __device__ inline int xcd_block_i8(int h, int nblk) {
   const int x = h & 7, k = h >> 3, q = nblk >> 3, rem = nblk & 7;
@@ -100,7 +82,7 @@ __global__ __launch_bounds__(256, 2) void pair_gemm_i8_kernel(PairSlicedArgs a) 
   // (recomputed per load: a few integer operations instead of 2 NS live registers)
   auto src_off = [&](int m) -> uint32_t {
     const int u = 64 * m + lane, r = u / SLOTS, ps = u - r * SLOTS;
-    return (uint32_t)(r * ROWB + 16 * logical_slot<NS>(r, ps));
+    return (uint32_t)(r * ROWB + 16 * i8l::logical_slot<NS>(r, ps));
   };
   auto load_chunk = [&](int chunk, u4* buf) {
     if (!load_w) return;
@@ -123,8 +105,8 @@ __global__ __launch_bounds__(256, 2) void pair_gemm_i8_kernel(PairSlicedArgs a) 
   const int nchunk = a.n_aux_pad / KC;
   const int r32 = lane & 31, hq = lane >> 5;
   const int rowA = wr * 32 + r32, rowB = wc * 32 + r32;
-  auto offA = [&](int t) { return rowA * SLOTS + phys_slot<NS>(rowA, 2 * t + hq); };
-  auto offB = [&](int t) { return rowB * SLOTS + phys_slot<NS>(rowB, 2 * t + hq); };
+  auto offA = [&](int t) { return rowA * SLOTS + i8l::phys_slot<NS>(rowA, 2 * t + hq); };
+  auto offB = [&](int t) { return rowB * SLOTS + i8l::phys_slot<NS>(rowB, 2 * t + hq); };
 
   // one chunk: the NS (NS+1)/2 digit products of levels < NS for P, then for Q
   auto compute = [&](const u4* buf) {
