@@ -513,7 +513,9 @@ def main():
     peak = PEAK_TFLOPS[dtype]
     kname = {"int8": "i8"}.get(args.precision, args.precision)
     split_epi = prof["pair_epilogue"][1] > 0
-    if split_epi:
+    if split_epi and args.precision == "int8":
+        kid, kdesc = f"pair_v_i8_kernel<{ns1},3>", "pair_v_i8 (V = B_i B_j^T, 128 x 128 tiles"
+    elif split_epi:
         kid, kdesc = f"pair_v_bf16_kernel<{ns1},4,4>", "pair_v_bf16 (V = B_i B_j^T, 128 x 128 tiles"
     else:
         kid = f"pair_gemm_{kname}_kernel<{ns1},true>"

@@ -27,6 +27,9 @@ CASES = [
     ("ragged_odd", (7, 0, 131, 77), 0.5),
     ("tiles_ragged", (12, 0, 200, 256), 1.0),
     ("one_hole", (1, 0, 70, 33), 0.8),
+    # one hole, three 128-row tile rows: every pair is i == j, whose V^{ii} the product
+    # kernel forms only on and above the diagonal (the epilogue takes Q from P)
+    ("one_hole_tiles", (1, 0, 300, 96), 0.5),
     ("active", (6, 4, 90, 140), 0.5),
 ]
 
