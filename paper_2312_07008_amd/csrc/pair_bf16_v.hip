@@ -10,7 +10,10 @@
 //                         regularizer / energy / density-row epilogue of
 //                         pair_epilogue.h, which (STORE) overwrites V with T in
 //                         place, or (energy-only passes) only forms the energy
-//                         and norm partials.
+//                         and norm partials.  It also serves the INT8-digit
+//                         product (pair_i8_v.hip).  The D_vv pass with the
+//                         split-BF16 density runs epi_split_bf16.hip instead,
+//                         which writes the density operands' slices.
 //
 // Operands come from split.hip: each FP64 row of B is sum_t slice_t with
 // slice_t an 8-bit integer times 2^(E - 8 - 9(t-1)).  The product of two rows

@@ -1,8 +1,9 @@
-// Epilogue shared by the sliced pair kernels (BF16 slices in pair_bf16_v.hip,
-// INT8 digits in pair_i8.hip): once a workgroup holds P = V^{ij}[I,J] and
-// Q = V^{ji}[I,J] of its tile pair in FP64, the DSRG regularizer, amplitudes and
-// energy partials follow the paper's App. A (Eq. A7), exactly as in the FP64 pair
-// kernel, plus the row data of the split-BF16 density.
+// Epilogue shared by the sliced pair kernels (the epilogue kernel of
+// pair_bf16_v.hip after the BF16 or INT8 product, the fused INT8 kernel of
+// pair_i8.hip): once a workgroup holds P = V^{ij}[I,J] and Q = V^{ji}[I,J] of its
+// tile pair in FP64, the DSRG regularizer, amplitudes and energy partials follow
+// the paper's App. A (Eq. A7), exactly as in the FP64 pair kernel, plus the row
+// data of the INT8-digit density.
 //
 // Register layout (any 32x32 MFMA accumulator): register r of lane l holds row
 // 8 (r / 4) + 4 (l / 32) + r % 4 and column l % 32 of the wave's 32 x 32 block;
@@ -13,7 +14,7 @@
 
 namespace dfpt2 {
 
-// Row information the split-BF16 density needs, from the amplitudes of one tile
+// Row information the INT8-digit density needs, from the amplitudes of one tile
 // pair (x = T[a][b] for a in I, b in J, y = T[b][a]; split_t.hip):
 //   the largest magnitudes of the rows of T, T^T, 2T - T^T and 2T^T - T
 //   (quantities |x|, |y|, |2x - y|, |2y - x| over b for rows a of I; with the
