@@ -320,10 +320,12 @@ def screen_gain(W, margin, s, p_o, prec, steps=3):
     mk = sc["mask"]
     dropped = [(i, j) for i in range(n_core) for j in range(i, n_core) if mk[i, j] == 0]
     wrong = sum(1 for i, j in dropped if not tn64[i, j] < SCREEN_THRESHOLD)
+    below = sum(1 for i in range(n_core) for j in range(i, n_core) if tn64[i, j] < SCREEN_THRESHOLD)
     return {"workload": "c4loc: 80 core holes, 1200 virtuals, 4000 auxiliary functions, localized holes and "
                         "auxiliary functions (xi = 1.25), seed 0",
             "threshold": SCREEN_THRESHOLD, "pairs_total": n_up, "pairs_dropped": sc["nd"],
             "pairs_dropped_above_threshold_in_fp64_pass": wrong,
+            "pairs_below_threshold_in_fp64_pass": below,
             "ms_per_pass_unscreened": u["ms"], "ms_per_pass_screened": sc["ms"],
             "speedup_screened_vs_unscreened": u["ms"] / sc["ms"], "fp64_ms_per_pass": fp64_ms,
             "speedup_screened_vs_fp64": fp64_ms / sc["ms"],
