@@ -406,12 +406,13 @@ enum {
   DFPT2_STAGE_ACTIVE = 4,     /* active-index rotation and active-pair energy */
   DFPT2_STAGE_EIGH = 5,       /* symmetric eigensolver */
   DFPT2_STAGE_TRANSFORM = 6,  /* recanonicalization GEMMs and B transform */
-  DFPT2_STAGE_KEPT_PAIR = 7,  /* pair kernel of the kept-space energy */
+  DFPT2_STAGE_KEPT_PAIR = 7,  /* pair kernels of the kept-space energy (product and epilogue) */
   DFPT2_STAGE_SCREEN = 8,     /* pair features, MLP, mask compaction */
   DFPT2_STAGE_SPLIT_T = 9,    /* amplitude splitting into BF16 slices for the density */
   DFPT2_STAGE_LADDER_TRANSFORM = 10, /* particle-particle ladder: inputs to the kept NO basis */
   DFPT2_STAGE_LADDER = 11,    /* particle-particle ladder: integral and contraction GEMMs */
-  DFPT2_STAGE_PAIR_EPILOGUE = 12, /* regularizer/energy epilogue run as a kernel of its own */
+  DFPT2_STAGE_PAIR_EPILOGUE = 12, /* the D_vv pass's regularizer/energy epilogue, where it runs as
+                                     a kernel of its own */
   DFPT2_NSTAGE = 13
 };
 int dfpt2_profile_enable(int on);

@@ -335,6 +335,14 @@ int default_slices_gemm1(int precision) {
 hipError_t launch_pair(const PairLaunch& L, const PairKernelArgs& a, int n_pairs, hipStream_t st,
                        ProfScope* product) {
   if (L.precision == DFPT2_FP64) return launch_pair_gemm_f64(a, n_pairs, st);
+  // an epilogue kernel of its own is timed as a stage of its own after the main
+  // pass's product; in the kept-space energy and the active blocks it stays in the
+  // caller's stage
+  const bool own_epi = product && product->stage() == DFPT2_STAGE_PAIR;
+  auto epi_stage = [&] {
+    if (own_epi) product->close();
+    return own_epi ? DFPT2_STAGE_PAIR_EPILOGUE : -1;
+  };
   PairSlicedArgs b{};
   b.Bs = L.Bs;
   b.scales = L.scales;
@@ -366,22 +374,19 @@ hipError_t launch_pair(const PairLaunch& L, const PairKernelArgs& a, int n_pairs
     }
     const hipError_t e = launch_pair_v_i8(b, L.ns, n_pairs, st);
     if (e != hipSuccess) return e;
-    if (product) product->close();
-    ProfScope ps(DFPT2_STAGE_PAIR_EPILOGUE, st);
+    ProfScope ps(epi_stage(), st);
     return launch_pair_epi_bf16(b, n_pairs, store, st);
   }
   if (L.ts && b.T && !b.Vr) {  // split-BF16 density: V in b.T, then the epilogue that slices the amplitudes
     const hipError_t e = launch_pair_v_bf16(b, L.ns, n_pairs, st);
     if (e != hipSuccess) return e;
-    if (product) product->close();
-    ProfScope ps(DFPT2_STAGE_PAIR_EPILOGUE, st);
+    ProfScope ps(epi_stage(), st);
     return launch_pair_epi_split_bf16(b, n_pairs, L.ns2, L.rows_t, L.ts, L.dgp, st);
   }
   if (b.T || b.Vr) {  // amplitudes stored: product and epilogue as two kernels
     const hipError_t e = launch_pair_v_bf16(b, L.ns, n_pairs, st);
     if (e != hipSuccess) return e;
-    if (product) product->close();
-    ProfScope ps(DFPT2_STAGE_PAIR_EPILOGUE, st);
+    ProfScope ps(epi_stage(), st);
     return launch_pair_epi_bf16(b, n_pairs, true, st);
   }
   if (L.vbuf) {  // energy only, with a V buffer: the same two kernels, nothing stored

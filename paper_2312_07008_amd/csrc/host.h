@@ -72,18 +72,21 @@ struct PairLaunch {
 };
 class ProfScope;
 // `product` (may be null): the caller's timer of the pair product; where the
-// epilogue runs as a kernel of its own, it is closed after the product and the
-// epilogue is timed as DFPT2_STAGE_PAIR_EPILOGUE
+// epilogue runs as a kernel of its own and that timer is the main pass's
+// (DFPT2_STAGE_PAIR), it is closed after the product and the epilogue is timed as
+// DFPT2_STAGE_PAIR_EPILOGUE; otherwise the epilogue stays in the caller's stage
 hipError_t launch_pair(const PairLaunch& L, const PairKernelArgs& a, int n_pairs, hipStream_t st,
                        ProfScope* product = nullptr);
 int default_slices_gemm1(int precision);
 
-// Stage timer scope (see dfpt2_profile_enable); no-op unless profiling is on.
+// Stage timer scope (see dfpt2_profile_enable); no-op unless profiling is on, and
+// for a negative stage.
 class ProfScope {
  public:
   ProfScope(int stage, hipStream_t s);
   ~ProfScope() { close(); }
   void close();  // records the end event now; later calls and the destructor do nothing
+  int stage() const { return stage_; }
  private:
   int stage_;
   hipStream_t s_;

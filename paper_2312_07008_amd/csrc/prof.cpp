@@ -38,7 +38,7 @@ hipEvent_t get_event() {
 }  // namespace
 
 ProfScope::ProfScope(int stage, hipStream_t s) : stage_(stage), s_(s), a_(nullptr) {
-  if (!g_prof.on) return;
+  if (!g_prof.on || stage < 0) return;
   a_ = get_event();
   if (a_ && hipEventRecord(a_, s_) != hipSuccess) a_ = nullptr;
 }
