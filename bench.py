@@ -335,6 +335,39 @@ def screen_gain(W, margin, s, p_o, prec, steps=3):
             "n_kept": {"screened": sc["n_kept"], "unscreened": u["n_kept"], "fp64": t64["n_kept"]}}
 
 
+def library_gemm_context(n_v, n_aux, batch=64):
+    """The vendor library's BF16 GEMM (torch.matmul / bmm on hipBLASLt) timed on this
+    part, for context beside the product kernel's fraction: one slice product of a
+    batch of pairs at the pass's own shape (n_v x n_v x n_aux) and one large square
+    GEMM.  Not part of the pass; contiguous operands only."""
+    import torch
+    out = []
+    for (m, n, k, nb) in ((n_v, n_v, n_aux, batch), (8192, 8192, 8192, 1)):
+        a = torch.randn(nb, m, k, device="cuda", dtype=torch.bfloat16)
+        b = torch.randn(nb, k, n, device="cuda", dtype=torch.bfloat16)
+        f = (lambda: torch.matmul(a[0], b[0])) if nb == 1 else (lambda: torch.bmm(a, b))
+        # warm-up of about 100 ms (the clock settles under load), then at least 100 ms timed
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        ev[0].record()
+        f()
+        ev[1].record()
+        torch.cuda.synchronize()
+        reps = max(10, int(100.0 / max(ev[0].elapsed_time(ev[1]), 1e-3)))
+        for _ in range(reps):
+            f()
+        ev[0].record()
+        for _ in range(reps):
+            f()
+        ev[1].record()
+        torch.cuda.synchronize()
+        ms = ev[0].elapsed_time(ev[1]) / reps
+        tf = 2.0 * m * n * k * nb / ms / 1e9
+        out.append({"m": m, "n": n, "k": k, "batch": nb, "reps": reps, "ms": ms, "TFLOP_s": tf, "frac": tf / PEAK_TFLOPS["bf16"]})
+        del a, b
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -355,6 +388,8 @@ def main():
     ap.add_argument("--no-screen-gain", action="store_true",
                     help="skip the screened-vs-unscreened measurement on the localized workload (c4loc) that a "
                          "default c4 run reports in screen_gain")
+    ap.add_argument("--no-library-gemm", action="store_true",
+                    help="skip the vendor BF16 GEMM timed beside a BF16 run for context")
     ap.add_argument("--no-alt", action="store_true",
                     help="skip the INT8-digit measurement reported beside a BF16 run")
     ap.add_argument("--ladder", action="store_true",
@@ -619,6 +654,10 @@ def main():
         log(f"INT8 digits: {out['alt_int8']['ms_per_pass']:.1f} ms per pass, kept {t8['n_kept']}")
         del ws8, D8
         torch.cuda.empty_cache()
+    if prec == dp.BF16_SLICED and not args.no_library_gemm:
+        out["library_gemm_context"] = library_gemm_context(-(-n_v // 128) * 128, n_aux)
+        log("library BF16 GEMM: " + ", ".join(f"{g['m']}x{g['n']}x{g['k']} x{g['batch']} {g['frac']:.3f}"
+                                                for g in out["library_gemm_context"]))
     if screen and args.workload == "c4" and not args.no_screen_gain:
         del ws_pass, ws_fno, ws_corr
         torch.cuda.empty_cache()
