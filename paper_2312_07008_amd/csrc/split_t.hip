@@ -49,8 +49,9 @@ using amp::u4;
 // four matrices.  x = T[a][c] comes straight from global memory, y = T[c][a]
 // from the mirror tile T[C, A] staged in LDS (amp::load_tile).  The thread's 16
 // columns are exactly one 16-wide chunk of the output row, so its slices of each
-// matrix (32 NS contiguous bytes) are stored straight from registers; the four
-// threads of a row write 128 NS contiguous bytes.
+// matrix (32 NS contiguous bytes) are stored from registers (for even NS after an
+// exchange within the row's quad, amp::split_block_row); the four threads of a row
+// write 128 NS contiguous bytes.
 template <int NS, bool VEC>
 __global__ __launch_bounds__(256) void split_t_bf16_kernel(const double* T, const int* slot, int n_v, int n_v_pad,
                                                            int rows_pad, int nt, double* dgp, __bf16* out) {
