@@ -24,6 +24,7 @@ CASES = [
     ("ragged_odd", (7, 0, 131, 77), 0.5),      # odd n_v and n_aux: scalar load paths, ragged tiles
     ("tiles_ragged", (12, 0, 200, 256), 1.0),  # several tiles + ragged tail
     ("one_hole", (1, 0, 70, 33), 0.8),          # single pair, symmetric amplitudes
+    ("aligned", (6, 0, 256, 128), 0.5),         # n_v a multiple of every tile edge: no padding
 ]
 
 

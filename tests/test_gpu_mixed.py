@@ -23,6 +23,9 @@ CASES = [
     # one hole, three 128-row tile rows: every pair is i == j, whose V^{ii} the product
     # kernel computes only on and above the diagonal (the epilogue takes Q from P)
     ("one_hole_tiles", (1, 0, 300, 96), 0.5),
+    # n_v a multiple of the 128-row tile (no padding rows or columns anywhere) and an
+    # auxiliary count that is a whole number of contraction chunks
+    ("aligned", (6, 0, 256, 128), 0.5),
 ]
 
 
