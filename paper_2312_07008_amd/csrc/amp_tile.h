@@ -24,32 +24,6 @@ __device__ inline double quad_xor(double v) {
   const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xf, 0xf, false);
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
-template <int CTRL>
-__device__ inline u4 quad_xor_u4(u4 v) {  // CTRL 0xB1: partner k ^ 1, 0x4E: partner k ^ 2
-  u4 r;
-  r.x = (uint32_t)__builtin_amdgcn_mov_dpp((int)v.x, CTRL, 0xf, 0xf, false);
-  r.y = (uint32_t)__builtin_amdgcn_mov_dpp((int)v.y, CTRL, 0xf, 0xf, false);
-  r.z = (uint32_t)__builtin_amdgcn_mov_dpp((int)v.z, CTRL, 0xf, 0xf, false);
-  r.w = (uint32_t)__builtin_amdgcn_mov_dpp((int)v.w, CTRL, 0xf, 0xf, false);
-  return r;
-}
-// one butterfly round of a quad transpose between items a and b (b = a + k of the
-// partner k4 ^ k): the lane with bit k of k4 set sends a and takes the partner's b
-// into a, the other sends b and takes the partner's a into b
-template <int CTRL>
-__device__ inline void quad_swap(u4& a, u4& b, bool hi) {
-  const u4 rcv = quad_xor_u4<CTRL>(hi ? a : b);
-  if (hi) a = rcv;
-  else b = rcv;
-}
-// 4 x 4 transpose over the quad: item t of lane k becomes item k of lane t
-__device__ inline void quad_transpose(u4& m0, u4& m1, u4& m2, u4& m3, int k4) {
-  const bool h1 = (k4 & 1) != 0, h2 = (k4 & 2) != 0;
-  quad_swap<0xB1>(m0, m1, h1);
-  quad_swap<0xB1>(m2, m3, h1);
-  quad_swap<0x4E>(m0, m2, h2);
-  quad_swap<0x4E>(m1, m3, h2);
-}
 // maximum / sum over the quad, the same pattern in every lane (reproducible)
 __device__ inline double quad_max(double v) {
   v = fmax(v, quad_xor<0xB1>(v));
@@ -144,17 +118,28 @@ __device__ inline void load_tile(const double* M, int n_v, int A, int C, double 
 // sum_t s_t 512^(ns-1-t) = rint(v 2^(8 + 9(ns-1) - E)).
 // Within a block every product of a row of X and a row of Y is an integer
 // multiple of one unit, so the density kernel's FP32 level sums over a block are
-// exact.  dst[m] points at the thread's 16-column chunk of row a of matrix m:
-// [ns][16] bf16, 32 ns contiguous bytes, the quad's four chunks contiguous.  For
-// even ns the quad exchanges its 16-byte pieces first (quad_transpose), so that
-// in each store the four lanes write 64 contiguous bytes instead of 16 bytes in
-// each of four 128-byte lines (the density pass's epilogue: 8.8 -> 7.2 ms per
-// 512-pair launch at 1200 virtuals).
-// Returns the row's diagonal partial sum_c 2 (x^2 - x y + y^2) over the block
-// (quad sum).  All four lanes of every quad must call this, with no lane
-// inactive.
+// exact.
+//
+// The workgroup (256 threads, thread t on row t / 4 of the 64-row tile, columns
+// 16 (t % 4) .. + 15 of the 64-column block) writes the block of the four
+// matrices: base is row 0 of the tile at the block's first column in matrix 0,
+// matrix m at base + m mat_elems, rows row_elems apart; a row of the block is
+// [4 chunks][ns][16] bf16, 128 ns contiguous bytes.  Each matrix's slices go
+// through the LDS buffer stg (at least 64 x 8 ns 16-byte pieces, the caller's
+// tile, free on entry up to the first barrier) so that every store of a wave
+// covers whole rows of the block: two 512-byte runs at ns = 4 instead of
+// sixteen lanes' 16-byte pieces in as many rows (the density pass's epilogue,
+// 512-pair launches at 1200 virtuals: 8.8 ms with per-thread stores, 7.2 with
+// the pieces exchanged within each row's four threads, 6.4 staged this way).  In LDS the piece p of
+// row r sits at slot (p + r) mod 8 ns, so that the writes and the reads of a
+// wave spread over all banks.  Returns the row's diagonal partial
+// sum_c 2 (x^2 - x y + y^2) over the block (quad sum).  Every thread of the
+// workgroup must call this: it holds barriers.
 template <int NS>
-__device__ inline double split_block_row(const double* x, const double* y, __bf16* const* dst) {
+__device__ inline double split_block_rows(const double* x, const double* y, u4* stg, __bf16* base,
+                                          size_t mat_elems, size_t row_elems) {
+  constexpr int SL = 8 * NS;  // 16-byte pieces per row of the block
+  const int tid = threadIdx.x, r = tid >> 2, k4 = tid & 3;
   double dg = 0.0;
 #pragma unroll
   for (int j = 0; j < 16; ++j) dg += 2.0 * (x[j] * x[j] - x[j] * y[j] + y[j] * y[j]);
@@ -170,40 +155,32 @@ __device__ inline double split_block_row(const double* x, const double* y, __bf1
     mx = quad_max(mx);
     int E = 0;
     if (mx > 0.0) frexp(mx, &E);  // mx < 2^E
-    bf8v sl[NS][2];
+    __syncthreads();  // every earlier read of stg is done
+    // columns 8 h .. 8 h + 7 form piece (t, h) of every slice t: staged half a chunk
+    // at a time, so that only NS pieces are held
 #pragma unroll
-    for (int j = 0; j < 16; ++j) {
-      double u = ldexp(v[j], 8 - E);
+    for (int h = 0; h < 2; ++h) {
+      bf8v sl[NS];
 #pragma unroll
-      for (int t = 0; t < NS; ++t) {
-        const double d = rint(u);
-        sl[t][j >> 3][j & 7] = (__bf16)ldexpf((float)d, E - 8 - 9 * t);
-        if (t + 1 < NS) u = (u - d) * 512.0;
+      for (int jj = 0; jj < 8; ++jj) {
+        const int j = 8 * h + jj;
+        double u = ldexp(v[j], 8 - E);
+#pragma unroll
+        for (int t = 0; t < NS; ++t) {
+          const double d = rint(u);
+          sl[t][jj] = (__bf16)ldexpf((float)d, E - 8 - 9 * t);
+          if (t + 1 < NS) u = (u - d) * 512.0;
+        }
       }
+#pragma unroll
+      for (int t = 0; t < NS; ++t) stg[r * SL + (k4 * 2 * NS + 2 * t + h + r) % SL] = __builtin_bit_cast(u4, sl[t]);
     }
-    u4* o = reinterpret_cast<u4*>(dst[m]);
-    if constexpr (NS % 2 == 0) {
-      // piece q = 2t + h of lane c sits at u4 2 NS c + q of the quad's region; store i
-      // of lane k4 writes u4 4 i + k4, i.e. piece 4 (i % G) + k4 of lane i / G (G = NS / 2)
-      constexpr int G = NS / 2;
-      const int k4 = threadIdx.x & 3;
-      u4* oq = o - 2 * NS * k4;
+    __syncthreads();
+    char* mb = reinterpret_cast<char*>(base + m * mat_elems);
 #pragma unroll
-      for (int g = 0; g < G; ++g) {
-        u4 p0 = __builtin_bit_cast(u4, sl[2 * g][0]), p1 = __builtin_bit_cast(u4, sl[2 * g][1]);
-        u4 p2 = __builtin_bit_cast(u4, sl[2 * g + 1][0]), p3 = __builtin_bit_cast(u4, sl[2 * g + 1][1]);
-        quad_transpose(p0, p1, p2, p3, k4);  // p_c = piece 4 g + k4 of lane c
-        oq[4 * g + k4] = p0;
-        oq[4 * (G + g) + k4] = p1;
-        oq[4 * (2 * G + g) + k4] = p2;
-        oq[4 * (3 * G + g) + k4] = p3;
-      }
-    } else {
-#pragma unroll
-      for (int t = 0; t < NS; ++t) {
-        o[2 * t] = __builtin_bit_cast(u4, sl[t][0]);
-        o[2 * t + 1] = __builtin_bit_cast(u4, sl[t][1]);
-      }
+    for (int i = 0; i < SL / 4; ++i) {  // 64 SL pieces over 256 threads
+      const int P = i * 256 + tid, row = P / SL, sp = P - row * SL;
+      *reinterpret_cast<u4*>(mb + (size_t)row * row_elems * 2 + sp * 16) = stg[row * SL + (sp + row) % SL];
     }
   }
   return quad_sum(dg);

@@ -18,7 +18,7 @@
 //
 // The thread's values then give the slices of rows a (columns of J) of the four
 // operands T, T^T, 2T - T^T, 2T^T - T with one exponent per (row, 64-column
-// block) (amp::split_block_row: the block is whole in the workgroup), and the
+// block) (amp::split_block_rows: the block is whole in the workgroup), and the
 // diagonal partial of row a for block J.  For I < J the amplitudes go through
 // LDS once more, so that every thread also holds 16 columns (of I) of a row of J
 // and writes those slices and that partial: each amplitude is read once, as V,
@@ -46,7 +46,7 @@ __global__ __launch_bounds__(256, 3) void pair_epi_split_bf16_kernel(PairSlicedA
                                                                      double* dgp) {
   // V[J, I] (the mirror), then in turn T[b][a] and T[a][b] at [a - 64 I][b - 64 J]:
   // one tile of LDS, so that three workgroups fit on a CU
-  __shared__ double sq[TB][LD];
+  __shared__ __attribute__((aligned(16))) double sq[TB][LD];
   __shared__ double red[8];
   const int L = xcd_block_e(blockIdx.x, a.nTP * a.n_blk_pairs);
   const int p = L / a.nTP, tp = L - p * a.nTP;
@@ -87,18 +87,16 @@ __global__ __launch_bounds__(256, 3) void pair_epi_split_bf16_kernel(PairSlicedA
   const int n_v_pad = a.n_v_pad_d;
   const size_t row_elems = (size_t)n_v_pad * NS, mat_elems = (size_t)rows_pad * row_elems;
   __bf16* Tq = Ts + (size_t)p * 4 * mat_elems;
+  amp::u4* stg = reinterpret_cast<amp::u4*>(&sq[0][0]);  // 33 KB: the 32 KB of a block of slices fit
   {  // rows a of I, columns of J
-    __bf16* dst[4];
-#pragma unroll
-    for (int m = 0; m < 4; ++m)
-      dst[m] = Tq + m * mat_elems + (size_t)ra * row_elems + (size_t)(J * 4 + k4) * (NS * 16);
-    const double dg = amp::split_block_row<NS>(x, y, dst);
+    __bf16* base = Tq + (size_t)(I * TB) * row_elems + (size_t)(J * 4) * (NS * 16);
+    const double dg = amp::split_block_rows<NS>(x, y, stg, base, mat_elems, row_elems);
     if (k4 == 0 && ra < n_v) dgp[((size_t)p * a.nt + J) * n_v_pad + ra] = dg;
   }
   if (offdiag) {  // workgroup-uniform
     // rows b = 64 J + r of J, columns a = 64 I + 16 k4 + j: T[b][a] and T[a][b],
     // transposed through the one LDS tile
-    __syncthreads();  // every read of the mirror V in sq is done
+    __syncthreads();  // every read of the staged slices in sq is done
 #pragma unroll
     for (int j = 0; j < 16; ++j) sq[r][16 * k4 + j] = y[j];
     __syncthreads();
@@ -118,11 +116,8 @@ __global__ __launch_bounds__(256, 3) void pair_epi_split_bf16_kernel(PairSlicedA
       y[j] = t;
     }
     const int rb = J * TB + r;
-    __bf16* dst[4];
-#pragma unroll
-    for (int m = 0; m < 4; ++m)
-      dst[m] = Tq + m * mat_elems + (size_t)rb * row_elems + (size_t)(I * 4 + k4) * (NS * 16);
-    const double dg = amp::split_block_row<NS>(x, y, dst);
+    __bf16* base = Tq + (size_t)(J * TB) * row_elems + (size_t)(I * 4) * (NS * 16);
+    const double dg = amp::split_block_rows<NS>(x, y, stg, base, mat_elems, row_elems);
     if (k4 == 0 && rb < n_v) dgp[((size_t)p * a.nt + I) * n_v_pad + rb] = dg;
   }
 

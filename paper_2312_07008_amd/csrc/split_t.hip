@@ -48,14 +48,13 @@ using amp::u4;
 // Workgroup = (row block A, column block C, pair q): rows A x columns C of the
 // four matrices.  x = T[a][c] comes straight from global memory, y = T[c][a]
 // from the mirror tile T[C, A] staged in LDS (amp::load_tile).  The thread's 16
-// columns are exactly one 16-wide chunk of the output row, so its slices of each
-// matrix (32 NS contiguous bytes) are stored from registers (for even NS after an
-// exchange within the row's quad, amp::split_block_row); the four threads of a row
-// write 128 NS contiguous bytes.
+// columns are exactly one 16-wide chunk of the output row; the slices of each
+// matrix go through the LDS tile to whole-row stores (amp::split_block_rows).
 template <int NS, bool VEC>
 __global__ __launch_bounds__(256) void split_t_bf16_kernel(const double* T, const int* slot, int n_v, int n_v_pad,
                                                            int rows_pad, int nt, double* dgp, __bf16* out) {
-  __shared__ double tm[TB][LD];  // T[C-block row][A-block col]
+  // T[C-block row][A-block col], then the staged slices
+  __shared__ __attribute__((aligned(16))) double tm[TB][LD];
   const int A = blockIdx.x / nt, C = blockIdx.x - (blockIdx.x / nt) * nt, q = blockIdx.y;
   const double* Tp = T + (size_t)(slot ? slot[q] : q) * n_v * n_v;
   const int tid = threadIdx.x;
@@ -67,11 +66,8 @@ __global__ __launch_bounds__(256) void split_t_bf16_kernel(const double* T, cons
 #pragma unroll
   for (int j = 0; j < 16; ++j) y[j] = tm[k4 * 16 + j][r];
   const size_t row_elems = (size_t)n_v_pad * NS, mat_elems = (size_t)rows_pad * row_elems;
-  __bf16* dst[4];
-#pragma unroll
-  for (int m = 0; m < 4; ++m)
-    dst[m] = out + ((size_t)q * 4 + m) * mat_elems + (size_t)row * row_elems + (size_t)(C * 4 + k4) * (NS * 16);
-  const double dg = amp::split_block_row<NS>(x, y, dst);
+  __bf16* base = out + (size_t)q * 4 * mat_elems + (size_t)(A * TB) * row_elems + (size_t)(C * 4) * (NS * 16);
+  const double dg = amp::split_block_rows<NS>(x, y, reinterpret_cast<u4*>(&tm[0][0]), base, mat_elems, row_elems);
   if (k4 == 0 && row < n_v) dgp[((size_t)q * nt + C) * n_v_pad + row] = dg;
 }
 
