@@ -78,12 +78,16 @@ __global__ __launch_bounds__(256) void split_t_bf16_kernel(const double* T, cons
 // value 2^(E - 6) sum_t d_t 2^(-8t).  Layout, chunk-major as for B (split.hip):
 // [q][m][n_v_pad/32][n_v_pad][NS][32] bytes, and the row exponents E - 6 in
 // rexp[q][m][n_v_pad] (0 for zero rows).  Thread (row r, quarter k4) holds 16
-// consecutive columns, i.e. one half of a 32-wide chunk: one 16-byte store per digit.
+// consecutive columns, i.e. one half of a 32-wide chunk: one 16-byte piece per
+// digit.  The workgroup's part of a matrix is two contiguous runs (its two
+// chunks, 64 rows of 32 NS bytes each), so the pieces go through the LDS tile
+// and every store of a wave writes 1 KB contiguous.
 template <int NS, bool VEC>
 __global__ __launch_bounds__(256) void split_t_i8_kernel(const double* T, const int* slot, int n_v, int n_v_pad,
                                                          int nt, const unsigned long long* tmax, int8_t* out,
                                                          int* rexp) {
-  __shared__ double tm[TB][LD];  // T[C-block row][A-block col]
+  // T[C-block row][A-block col], then the staged digits
+  __shared__ __attribute__((aligned(16))) double tm[TB][LD];
   const int A = blockIdx.x / nt, C = blockIdx.x - (blockIdx.x / nt) * nt, q = blockIdx.y;
   const double* Tp = T + (size_t)(slot ? slot[q] : q) * n_v * n_v;
   const int tid = threadIdx.x;
@@ -96,7 +100,6 @@ __global__ __launch_bounds__(256) void split_t_i8_kernel(const double* T, const 
   for (int j = 0; j < 16; ++j) y[j] = tm[k4 * 16 + j][r];
 
   const int nck = n_v_pad >> 5;
-  const int ch = C * 2 + (k4 >> 1), kk0 = (k4 & 1) * 16;
 #pragma unroll
   for (int m = 0; m < 4; ++m) {
     const double mx = __longlong_as_double((long long)tmax[((size_t)q * 4 + m) * n_v_pad + row]);
@@ -120,7 +123,9 @@ __global__ __launch_bounds__(256) void split_t_i8_kernel(const double* T, const 
       }
       word[0][j >> 2] |= ((uint32_t)Z & 0xffu) << (8 * (j & 3));
     }
-    int8_t* dst = out + ((((size_t)q * 4 + m) * nck + ch) * n_v_pad + row) * (size_t)(32 * NS) + kk0;
+    // staged as [2 chunks][64 rows][2 NS pieces of 16 bytes]: 256 NS pieces
+    u4* stg = reinterpret_cast<u4*>(&tm[0][0]);
+    __syncthreads();  // every earlier read of tm is done
 #pragma unroll
     for (int t = 0; t < NS; ++t) {
       u4 v4;
@@ -128,7 +133,14 @@ __global__ __launch_bounds__(256) void split_t_i8_kernel(const double* T, const 
       v4[1] = word[t][1];
       v4[2] = word[t][2];
       v4[3] = word[t][3];
-      *reinterpret_cast<u4*>(dst + 32 * t) = v4;
+      stg[(k4 >> 1) * (128 * NS) + r * (2 * NS) + 2 * t + (k4 & 1)] = v4;
+    }
+    __syncthreads();
+    int8_t* mb = out + (((size_t)q * 4 + m) * nck + 2 * C) * n_v_pad * (size_t)(32 * NS);
+#pragma unroll
+    for (int i = 0; i < NS; ++i) {
+      const int P = i * 256 + tid, c2 = P / (128 * NS), off = P - c2 * (128 * NS);
+      *reinterpret_cast<u4*>(mb + ((size_t)c2 * n_v_pad + (size_t)A * TB) * (32 * NS) + (size_t)off * 16) = stg[P];
     }
   }
 }
