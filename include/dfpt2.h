@@ -398,12 +398,14 @@ int pairscreen_build_mask(const float* pred, const double* log_scale, int64_t n_
  *   launches  host out [DFPT2_NSTAGE], number of timed launches per stage
  */
 enum {
-  DFPT2_STAGE_PAIR = 0,       /* pair product V = B_i B_j^T (with the fused regularizer/energy
-                                 epilogue where the product and the epilogue share a kernel) */
-  DFPT2_STAGE_DENSITY = 1,    /* density kernel (D_vv accumulation) */
+  DFPT2_STAGE_PAIR = 0,       /* pair product V = B_i B_j^T of the core pairs (with the fused
+                                 regularizer/energy epilogue where the product and the epilogue
+                                 share a kernel) */
+  DFPT2_STAGE_DENSITY = 1,    /* density kernel (D_vv accumulation) of the core pairs */
   DFPT2_STAGE_SPLIT = 2,      /* operand splitting into BF16/FP8 slices */
   DFPT2_STAGE_REDUCE = 3,     /* pair lists, reductions, finalization */
-  DFPT2_STAGE_ACTIVE = 4,     /* active-index rotation and active-pair energy */
+  DFPT2_STAGE_ACTIVE = 4,     /* pairs with an active hole: their product, epilogue, rotation to the
+                                 natural active orbitals, energy, amplitude split and density */
   DFPT2_STAGE_EIGH = 5,       /* symmetric eigensolver */
   DFPT2_STAGE_TRANSFORM = 6,  /* recanonicalization GEMMs and B transform */
   DFPT2_STAGE_KEPT_PAIR = 7,  /* pair kernels of the kept-space energy (product and epilogue) */

@@ -401,7 +401,8 @@ hipError_t launch_pair(const PairLaunch& L, const PairKernelArgs& a, int n_pairs
 // Density of amplitude matrices already in memory (matrix p at T + slot[p] n_v^2)
 // with per-pair weights pw, on the pass's sliced path: row data (maxima and
 // diagonal partials), operand slices (BF16) or digits (INT8), then the sliced
-// density product accumulated into Dpart and the exact diagonal into diag.
+// density product accumulated into Dpart and the exact diagonal into diag.  Used
+// by the active blocks only, whose stage timer covers it: it opens none of its own.
 static int sliced_density(const PassPlan& pl, const double* T, const int* slot, const int2* pairs, const double* pw,
                           int np, double* Dpart, char* ws, hipStream_t s) {
   hipError_t e;
@@ -410,7 +411,6 @@ static int sliced_density(const PassPlan& pl, const double* T, const int* slot, 
   double* diag = reinterpret_cast<double*>(ws + pl.off_diag);
   if (pl.precision == DFPT2_INT8_SLICED) {
     {  // one exponent per row: the row maxima first
-      ProfScope ps(DFPT2_STAGE_SPLIT_T, s);
       if ((e = launch_fill(reinterpret_cast<double*>(tmax), (size_t)np * 4 * pl.n_v_pad_d, 0.0, s)) != hipSuccess)
         return hip_fail(e, "fill");
       if ((e = launch_pair_row_stats(T, slot, np, pl.n_v, pl.n_v_pad_d, tmax, dgp, s)) != hipSuccess)
@@ -419,7 +419,6 @@ static int sliced_density(const PassPlan& pl, const double* T, const int* slot, 
     int8_t* Ts = reinterpret_cast<int8_t*>(ws + pl.off_Ts);
     int* Texp = reinterpret_cast<int*>(ws + pl.off_Texp);
     {
-      ProfScope ps(DFPT2_STAGE_SPLIT_T, s);
       if ((e = launch_split_t_i8(T, slot, pairs, pw, 1.0, np, pl.n_v, pl.n_v_pad_d, pl.ns2, tmax, dgp, Ts, Texp, diag,
                                  s)) != hipSuccess)
         return hip_fail(e, "amplitude digits");
@@ -438,13 +437,11 @@ static int sliced_density(const PassPlan& pl, const double* T, const int* slot, 
     dd.nsplit = pl.nsplit2 < np ? pl.nsplit2 : np;
     dd.w = 1.0;
     dd.accumulate = 1;
-    ProfScope ps(DFPT2_STAGE_DENSITY, s);
     if ((e = launch_density_i8(dd, pl.ns2, s)) != hipSuccess) return hip_fail(e, "density kernel (INT8)");
     return DFPT2_OK;
   }
   __bf16* Ts = reinterpret_cast<__bf16*>(ws + pl.off_Ts);
   {
-    ProfScope ps(DFPT2_STAGE_SPLIT_T, s);
     if ((e = launch_split_t_bf16(T, slot, pairs, pw, 1.0, np, pl.n_v, pl.n_v_pad_d, pl.n_v_rows_t, pl.ns2, dgp, Ts,
                                  diag, s)) != hipSuccess)
       return hip_fail(e, "amplitude split");
@@ -463,7 +460,6 @@ static int sliced_density(const PassPlan& pl, const double* T, const int* slot, 
   ds.nsplit = pl.nsplit2 < np ? pl.nsplit2 : np;
   ds.w = 1.0;
   ds.accumulate = 1;
-  ProfScope ps(DFPT2_STAGE_DENSITY, s);
   if ((e = launch_density_bf16(ds, pl.ns2, s)) != hipSuccess) return hip_fail(e, "density kernel (BF16)");
   return DFPT2_OK;
 }
