@@ -404,11 +404,13 @@ enum {
   DFPT2_STAGE_DENSITY = 1,    /* density kernel (D_vv accumulation) of the core pairs */
   DFPT2_STAGE_SPLIT = 2,      /* operand splitting into BF16/FP8 slices */
   DFPT2_STAGE_REDUCE = 3,     /* pair lists, reductions, finalization */
-  DFPT2_STAGE_ACTIVE = 4,     /* pairs with an active hole: their product, epilogue, rotation to the
-                                 natural active orbitals, energy, amplitude split and density */
+  DFPT2_STAGE_ACTIVE = 4,     /* pairs with an active hole in the D_vv pass: their product, epilogue,
+                                 rotation to the natural active orbitals, energy, amplitude split
+                                 and density */
   DFPT2_STAGE_EIGH = 5,       /* symmetric eigensolver */
   DFPT2_STAGE_TRANSFORM = 6,  /* recanonicalization GEMMs and B transform */
-  DFPT2_STAGE_KEPT_PAIR = 7,  /* pair kernels of the kept-space energy (product and epilogue) */
+  DFPT2_STAGE_KEPT_PAIR = 7,  /* the kept-space energy's pair kernels (product and epilogue),
+                                 core and active holes */
   DFPT2_STAGE_SCREEN = 8,     /* pair features, MLP, mask compaction */
   DFPT2_STAGE_SPLIT_T = 9,    /* amplitude splitting into BF16 slices for the density */
   DFPT2_STAGE_LADDER_TRANSFORM = 10, /* particle-particle ladder: inputs to the kept NO basis */

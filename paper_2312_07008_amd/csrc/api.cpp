@@ -495,7 +495,8 @@ static int run_active_blocks(const PassPlan& pl, const dfpt2_opts& o, const doub
   // natural orbitals of the active density: Gamma_act = U diag(n) U^T
   int st = eigh_run(gamma_act, na, occ, Ua, ws + pl.off_act_eig, pl.act_eig_bytes, s, 0);
   if (st != DFPT2_OK) return st;
-  ProfScope prof(DFPT2_STAGE_ACTIVE, s);
+  // the kept-space energy (energy only) times its active blocks with its core pairs
+  ProfScope prof(pl.energy_only ? DFPT2_STAGE_KEPT_PAIR : DFPT2_STAGE_ACTIVE, s);
   if ((e = launch_kron_uu(Ua, na, Wk, s)) != hipSuccess) return hip_fail(e, "kron");
 
   PairKernelArgs pa{};
