@@ -657,9 +657,13 @@ def main():
         del ws8, D8
         torch.cuda.empty_cache()
     if prec == dp.BF16_SLICED and not args.no_library_gemm:
-        out["library_gemm_context"] = library_gemm_context(-(-n_v // 128) * 128, n_aux)
-        log("library BF16 GEMM: " + ", ".join(f"{g['m']}x{g['n']}x{g['k']} x{g['batch']} {g['frac']:.3f}"
-                                                for g in out["library_gemm_context"]))
+        try:  # context only: a failure here is recorded and does not stop the line
+            out["library_gemm_context"] = library_gemm_context(-(-n_v // 128) * 128, n_aux)
+            log("library BF16 GEMM: " + ", ".join(f"{g['m']}x{g['n']}x{g['k']} x{g['batch']} {g['frac']:.3f}"
+                                                    for g in out["library_gemm_context"]))
+        except RuntimeError as exc:
+            out["library_gemm_context"] = {"error": str(exc)[:200]}
+            torch.cuda.empty_cache()
     if screen and args.workload == "c4" and not args.no_screen_gain:
         del ws_pass, ws_fno, ws_corr
         torch.cuda.empty_cache()
